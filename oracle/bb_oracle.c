@@ -1,0 +1,300 @@
+/*
+ * bb_oracle.c -- plain, slow, sequential FP64 CPU oracle for band -> bidiagonal
+ * reduction by bulge chasing with successive band reduction.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header or table with the GPU
+ * path.  Build: gcc -O2 -ffp-contract=off -shared -fPIC (no FMA contraction,
+ * so every sum is evaluated left to right exactly as written).
+ *
+ * What it computes (paper: Sec. III, Algorithm 1 and its description; the
+ * dependency discussion in Sec. III-A; the storage paragraph of Sec. IV):
+ *   A is n x n upper banded with b super-diagonals.  The bandwidth is reduced
+ *   in stages of TW ("inner tilewidth", Alg. 1 outer loop): a stage with
+ *   bandwidth b uses tw = min(TW, b-1) and leaves bandwidth c = b - tw; stages
+ *   repeat until c = 1 (bidiagonal).  Within a stage, sweep r (Alg. 1 second
+ *   loop) first annihilates the tw entries A[r, r+c+1 .. r+b] with a right
+ *   (row) Householder reflector, which creates a bulge below the diagonal whose
+ *   left-most column is annihilated with a left (column) reflector (Alg. 1
+ *   third loop, two HH lines).  That left reflector creates a new row bulge
+ *   b rows further down, which the next step of the same sweep chases.  Only
+ *   the first row/column of each bulge is chased; the rest is left for later
+ *   sweeps (Sec. III, "excess bulges ... deferred").  Fill therefore stays
+ *   within tw sub-diagonals and b+tw super-diagonals, which is the band height
+ *   b + 2 tw + 1 stated in the storage paragraph of Sec. IV.
+ *
+ *   Step geometry (0-based; the paper omits index details in Alg. 2):
+ *     step 0 : row k = r, pivot p = r + c, m = min(r+b, n-1) - p  (sweep exists iff m >= 1)
+ *     step j : row k = r + c + (j-1) b, pivot p = k + b, m = min(tw, n-1-p); stop when m < 1
+ *   Each step: right reflector from A[k, p..p+m], applied to rows k+1..p+m;
+ *   then left reflector from A[p..p+m, p], applied to columns p+1..min(p+m+b, n-1).
+ *
+ *   Householder convention (the paper defers it to its tile-QR reference; we
+ *   take the LAPACK xLARFG definition): x = (alpha, x2); if ||x2|| == 0 then
+ *   H = I (tau = 0, beta = alpha); else beta = -sign(alpha) ||x|| with
+ *   sign(0) = +1, tau = (beta - alpha) / beta, v = x / (alpha - beta), v0 = 1,
+ *   and H = I - tau v v^T maps x to beta e1.  The annihilated entries are
+ *   written as exact zeros and beta is stored in place.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define BBO_MAXTW 4096
+
+typedef struct {
+    int64_t n, ldw, uo;   /* element (i,q) lives at w[(i - q + uo) + q * ldw] */
+    double *w;
+} bbo_band;
+
+static inline double *at(const bbo_band *B, int64_t i, int64_t q) {
+    return &B->w[(i - q + B->uo) + q * B->ldw];
+}
+
+/* Euclidean norm by the classic scaled sum of squares (reference BLAS xNRM2). */
+static double nrm2(const double *x, int64_t len) {
+    double scale = 0.0, ssq = 1.0;
+    for (int64_t t = 0; t < len; ++t) {
+        if (x[t] != 0.0) {
+            double ax = fabs(x[t]);
+            if (scale < ax) {
+                double q = scale / ax;
+                ssq = 1.0 + ssq * (q * q);
+                scale = ax;
+            } else {
+                double q = ax / scale;
+                ssq = ssq + q * q;
+            }
+        }
+    }
+    return scale * sqrt(ssq);
+}
+
+/* sqrt(a^2 + b^2) without avoidable overflow (LAPACK xLAPY2). */
+static double hypot2(double a, double b) {
+    double xa = fabs(a), ya = fabs(b);
+    double w = xa > ya ? xa : ya, z = xa < ya ? xa : ya;
+    if (z == 0.0) return w;
+    double q = z / w;
+    return w * sqrt(1.0 + q * q);
+}
+
+/* Householder generation: x[0..m] in, v[0..m], *tau, *beta out. */
+static void house(const double *x, int64_t m, double *v, double *tau, double *beta) {
+    double alpha = x[0];
+    double xn = nrm2(x + 1, m);
+    v[0] = 1.0;
+    if (xn == 0.0) {
+        for (int64_t t = 1; t <= m; ++t) v[t] = 0.0;
+        *tau = 0.0;
+        *beta = alpha;
+        return;
+    }
+    double h = hypot2(alpha, xn);
+    double bt = (alpha >= 0.0) ? -h : h;
+    double scal = 1.0 / (alpha - bt);
+    for (int64_t t = 1; t <= m; ++t) v[t] = x[t] * scal;
+    *tau = (bt - alpha) / bt;
+    *beta = bt;
+}
+
+/* dot of a strided sequence with v, in forward or reversed order */
+typedef struct { int rev; } bbo_opts;
+
+/* Right (row) task: reflector from A[k, p..p+m], applied to rows k+1..p+m. */
+static void task_right(bbo_band *A, int64_t k, int64_t p, int64_t m, const bbo_opts *o,
+                       double *V, int64_t ldv) {
+    double x[BBO_MAXTW + 1], v[BBO_MAXTW + 1], tau, beta;
+    for (int64_t t = 0; t <= m; ++t) x[t] = *at(A, k, p + t);
+    house(x, m, v, &tau, &beta);
+    *at(A, k, p) = beta;
+    for (int64_t t = 1; t <= m; ++t) *at(A, k, p + t) = 0.0;
+    if (tau == 0.0) return;
+    for (int64_t i = k + 1; i <= p + m; ++i) {
+        double w = 0.0;
+        if (!o->rev) for (int64_t t = 0; t <= m; ++t) w = w + *at(A, i, p + t) * v[t];
+        else         for (int64_t t = m; t >= 0; --t) w = w + *at(A, i, p + t) * v[t];
+        double tw = tau * w;
+        for (int64_t t = 0; t <= m; ++t) *at(A, i, p + t) = *at(A, i, p + t) - tw * v[t];
+    }
+    if (V) {  /* V <- V H on columns p..p+m (all rows) */
+        for (int64_t i = 0; i < A->n; ++i) {
+            double w = 0.0;
+            for (int64_t t = 0; t <= m; ++t) w = w + V[i + (p + t) * ldv] * v[t];
+            double tw = tau * w;
+            for (int64_t t = 0; t <= m; ++t) V[i + (p + t) * ldv] = V[i + (p + t) * ldv] - tw * v[t];
+        }
+    }
+}
+
+/* Left (column) task: reflector from A[p..p+m, p], applied to columns p+1..L. */
+static void task_left(bbo_band *A, int64_t b, int64_t p, int64_t m, const bbo_opts *o,
+                      double *U, int64_t ldu) {
+    double x[BBO_MAXTW + 1], v[BBO_MAXTW + 1], tau, beta;
+    int64_t L = p + m + b;
+    if (L > A->n - 1) L = A->n - 1;
+    for (int64_t t = 0; t <= m; ++t) x[t] = *at(A, p + t, p);
+    house(x, m, v, &tau, &beta);
+    *at(A, p, p) = beta;
+    for (int64_t t = 1; t <= m; ++t) *at(A, p + t, p) = 0.0;
+    if (tau == 0.0) return;
+    for (int64_t q = p + 1; q <= L; ++q) {
+        double w = 0.0;
+        if (!o->rev) for (int64_t t = 0; t <= m; ++t) w = w + v[t] * *at(A, p + t, q);
+        else         for (int64_t t = m; t >= 0; --t) w = w + v[t] * *at(A, p + t, q);
+        double tw = tau * w;
+        for (int64_t t = 0; t <= m; ++t) *at(A, p + t, q) = *at(A, p + t, q) - tw * v[t];
+    }
+    if (U) {  /* U <- U H on columns p..p+m (all rows) */
+        for (int64_t i = 0; i < A->n; ++i) {
+            double w = 0.0;
+            for (int64_t t = 0; t <= m; ++t) w = w + U[i + (p + t) * ldu] * v[t];
+            double tw = tau * w;
+            for (int64_t t = 0; t <= m; ++t) U[i + (p + t) * ldu] = U[i + (p + t) * ldu] - tw * v[t];
+        }
+    }
+}
+
+/* Step geometry of sweep r, step j in a stage (b, tw, c).  Returns m (< 1: no step). */
+static int64_t step_geom(int64_t n, int64_t b, int64_t tw, int64_t c, int64_t r, int64_t j,
+                         int64_t *k, int64_t *p) {
+    if (j == 0) {
+        *k = r;
+        *p = r + c;
+        int64_t last = r + b < n - 1 ? r + b : n - 1;
+        return last - *p;
+    }
+    *k = r + c + (j - 1) * b;
+    *p = *k + b;
+    int64_t m = n - 1 - *p;
+    return m < tw ? m : tw;
+}
+
+static int setup(int64_t n, int64_t *b, int64_t TW, const double *band, int64_t ldband,
+                 bbo_band *A, int64_t *tw0) {
+    if (n < 0) return -1;
+    if (*b < 0) return -2;
+    if (TW < 1 || TW > BBO_MAXTW) return -3;
+    if (!band && n > 0) return -4;
+    if (ldband < *b + 1) return -5;
+    int64_t bb = *b;
+    if (n > 0 && bb > n - 1) bb = n - 1;
+    int64_t tw = bb > 1 ? (TW < bb - 1 ? TW : bb - 1) : 0;
+    A->n = n;
+    A->uo = bb + tw > 1 ? bb + tw : 1;  /* room for the super-diagonal even when b = 0 */
+    A->ldw = A->uo + tw + 1;
+    A->w = (double *)calloc((size_t)(A->ldw * (n > 0 ? n : 1)), sizeof(double));
+    if (!A->w) return 1;
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = (j - bb > 0 ? j - bb : 0); i <= j; ++i)
+            *at(A, i, j) = band[(*b + i - j) + j * ldband];
+    *b = bb;
+    *tw0 = tw;
+    return 0;
+}
+
+static void extract(const bbo_band *A, double *d, double *e) {
+    for (int64_t i = 0; i < A->n; ++i) d[i] = *at(A, i, i);
+    for (int64_t i = 0; i + 1 < A->n; ++i) e[i] = *at(A, i, i + 1);
+}
+
+/*
+ * Sequential reduction: stage by stage, sweep r completely before sweep r+1.
+ * band: LAPACK upper band, A(i,j) = band[(b + i - j) + j*ldband], ldband >= b+1.
+ * d (n), e (n-1): outputs.  U, V: optional n x n column-major (ld n) arrays that
+ * receive the accumulated orthogonal factors, so that U^T A V = bidiag(d, e).
+ * rev != 0 evaluates every dot product in reversed order (a sensitivity probe).
+ * Returns 0, or -i for an invalid argument i, or 1 on allocation failure.
+ */
+int bbo_reduce(int64_t n, int64_t b, int64_t TW, const double *band, int64_t ldband,
+               double *d, double *e, double *U, double *V, int rev) {
+    bbo_band A;
+    int64_t tw0;
+    int rc = setup(n, &b, TW, band, ldband, &A, &tw0);
+    if (rc) return rc;
+    if (U) { memset(U, 0, sizeof(double) * n * n); for (int64_t i = 0; i < n; ++i) U[i + i * n] = 1.0; }
+    if (V) { memset(V, 0, sizeof(double) * n * n); for (int64_t i = 0; i < n; ++i) V[i + i * n] = 1.0; }
+    bbo_opts o = {rev};
+    int64_t bs = b;
+    while (bs > 1) {
+        int64_t tw = TW < bs - 1 ? TW : bs - 1, c = bs - tw;
+        for (int64_t r = 0; r + c + 1 <= n - 1; ++r) {
+            for (int64_t j = 0;; ++j) {
+                int64_t k, p, m = step_geom(n, bs, tw, c, r, j, &k, &p);
+                if (m < 1) break;
+                task_right(&A, k, p, m, &o, V, n);
+                task_left(&A, bs, p, m, &o, U, n);
+            }
+        }
+        bs = c;
+    }
+    extract(&A, d, e);
+    free(A.w);
+    return 0;
+}
+
+/*
+ * Host simulation of a pipelined execution (a race detector without a GPU).
+ * Half-step h = 2j is the right task of step j, h = 2j+1 its left task.  Half-
+ * step h of sweep r may run once sweep r-1 has completed half-steps 0..h+H-1,
+ * or is DONE; a sweep becomes DONE when all its half-steps ran and sweep r-1 is
+ * DONE.  H is lag[0] when c == 1, lag[1] when c == 2, lag[2] when c >= 3.  The
+ * ready tasks run in an order drawn from a xorshift64 stream seeded by `seed`.
+ * If the rule is safe, every such order gives results bitwise equal to
+ * bbo_reduce(), because tasks that may run concurrently touch disjoint data.
+ * Returns as bbo_reduce, or 2 if the rule deadlocks.
+ */
+int bbo_reduce_pipelined(int64_t n, int64_t b, int64_t TW, const double *band, int64_t ldband,
+                         double *d, double *e, const int *lag, uint64_t seed) {
+    bbo_band A;
+    int64_t tw0;
+    int rc = setup(n, &b, TW, band, ldband, &A, &tw0);
+    if (rc) return rc;
+    bbo_opts o = {0};
+    uint64_t s = seed ? seed : 0x9E3779B97F4A7C15ull;
+    int64_t *len = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
+    int64_t *prog = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
+    int64_t *ready = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
+    const int64_t DONE = INT64_MAX;
+    int64_t bs = b;
+    while (bs > 1 && rc == 0) {
+        int64_t tw = TW < bs - 1 ? TW : bs - 1, c = bs - tw;
+        int64_t H = c == 1 ? lag[0] : (c == 2 ? lag[1] : lag[2]);
+        int64_t ns = 0;
+        for (int64_t r = 0; r + c + 1 <= n - 1; ++r, ++ns) {
+            int64_t j = 0, k, p;
+            while (step_geom(n, bs, tw, c, r, j, &k, &p) >= 1) ++j;
+            len[r] = 2 * j;
+            prog[r] = 0;
+        }
+        int64_t first = 0;  /* lowest sweep not DONE; all below it are DONE */
+        while (first < ns) {
+            int64_t nr = 0;
+            for (int64_t r = first; r < ns; ++r) {
+                int dep = (r == 0) || prog[r - 1] == DONE || prog[r - 1] >= prog[r] + H;
+                if (prog[r] != DONE && prog[r] < len[r] && dep) ready[nr++] = r;
+                if (prog[r] == 0) break;  /* sweeps after an unstarted one cannot start */
+            }
+            if (nr == 0) { rc = 2; break; }
+            s ^= s << 13; s ^= s >> 7; s ^= s << 17;
+            int64_t r = ready[s % (uint64_t)nr];
+            int64_t h = prog[r], j = h / 2, k, p;
+            int64_t m = step_geom(n, bs, tw, c, r, j, &k, &p);
+            if (h % 2 == 0) task_right(&A, k, p, m, &o, NULL, 0);
+            else task_left(&A, bs, p, m, &o, NULL, 0);
+            prog[r] = h + 1;
+            /* DONE is transitive: a finished sweep becomes DONE once its predecessor is */
+            for (int64_t q = first; q < ns; ++q) {
+                if (prog[q] != DONE && prog[q] >= len[q] && (q == 0 || prog[q - 1] == DONE)) prog[q] = DONE;
+                if (prog[q] != DONE) break;
+            }
+            while (first < ns && prog[first] == DONE) ++first;
+        }
+        bs = c;
+    }
+    if (rc == 0) extract(&A, d, e);
+    free(len); free(prog); free(ready); free(A.w);
+    return rc;
+}

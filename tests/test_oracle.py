@@ -1,0 +1,208 @@
+"""Pins of the CPU oracle against facts fixed by the mathematics (CPU only).
+
+Each test targets a different class of plausible mistake:
+  * index ranges / storage      -> dense full-range coding equals the band oracle exactly
+  * arithmetic of reflectors    -> singular values vs brute-force Jacobi, Frobenius norm
+  * sign / transposed operands  -> U^T A V = B with orthogonal U, V
+  * Householder convention      -> closed forms d0 = a00, |e0| = ||A[0,1:]||, n = 3 formula
+  * zero handling (tau = 0)     -> already-bidiagonal input returned bitwise unchanged
+  * uniqueness (implicit Q)     -> |d|,|e| equal a textbook dense Golub-Kahan bidiagonalisation
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_12705_amd import inputs
+from tests.pins import band_to_dense, dense_to_band, golub_kahan_dense, jacobi_singular_values
+
+EPS = np.finfo(np.float64).eps
+
+
+def _bidiag(d, e):
+    n = len(d)
+    B = np.diag(d)
+    if n > 1:
+        B += np.diag(e, 1)
+    return B
+
+
+CASES = [(12, 3, 1), (12, 3, 2), (20, 5, 2), (24, 6, 2), (24, 6, 4), (31, 7, 3), (17, 16, 16),
+         (25, 8, 7), (30, 9, 1), (16, 4, 16), (9, 8, 3), (40, 12, 5)]
+
+
+@pytest.mark.parametrize("n,b,tw", CASES)
+def test_band_equals_dense_full_range(n, b, tw):
+    """Band oracle (exact application ranges) == pure-Python dense chase that applies every
+    reflector to every row and column; the dense result is exactly bidiagonal."""
+    band = inputs.band_normal(n, b, seed=100 + n + b + tw)
+    A = band_to_dense(band, n, b)
+    M = np.array(oracle.reduce_dense_full(A.tolist(), b, tw))
+    off = M - np.diag(np.diag(M)) - np.diag(np.diag(M, 1), 1)
+    assert np.count_nonzero(off) == 0, "dense full-range chase left off-bidiagonal entries"
+    d, e = oracle.reduce(band, n, b, tw)
+    assert np.array_equal(d, np.diag(M))
+    assert np.array_equal(e, np.diag(M, 1))
+
+
+@pytest.mark.parametrize("n,b,tw", [(40, 6, 2), (64, 10, 3), (48, 16, 16), (33, 32, 8)])
+def test_singular_values_vs_jacobi(n, b, tw):
+    band = inputs.band_normal(n, b, seed=7 + n)
+    A = band_to_dense(band, n, b)
+    d, e = oracle.reduce(band, n, b, tw)
+    s = oracle.singular_values(d, e)
+    sj = jacobi_singular_values(A)
+    assert np.max(np.abs(s - sj)) <= 4 * n * EPS * sj[0]
+    # library cross-check of the same dense matrix
+    sl = np.linalg.svd(A, compute_uv=False)
+    assert np.max(np.abs(s - sl)) <= 4 * n * EPS * sl[0]
+
+
+def test_singular_values_routine_vs_dense_svd():
+    """The TGK/dsterf routine applied to a bidiagonal equals a dense SVD of that bidiagonal."""
+    rng = np.random.default_rng(3)
+    d, e = rng.standard_normal(50), rng.standard_normal(49)
+    s = oracle.singular_values(d, e)
+    sl = np.linalg.svd(_bidiag(d, e), compute_uv=False)
+    assert np.max(np.abs(s - sl)) <= 10 * 50 * EPS * sl[0]
+
+
+@pytest.mark.parametrize("n,b,tw", [(64, 8, 3), (100, 16, 16), (96, 24, 5)])
+def test_frobenius_preserved(n, b, tw):
+    band = inputs.band_uniform(n, b, seed=11)
+    A = band_to_dense(band, n, b)
+    d, e = oracle.reduce(band, n, b, tw)
+    lhs = np.sum(d * d) + np.sum(e * e)
+    rhs = np.sum(A * A)
+    assert abs(lhs - rhs) <= 10 * n * EPS * rhs
+
+
+@pytest.mark.parametrize("n,b,tw", [(30, 5, 2), (48, 9, 4), (40, 12, 11)])
+def test_orthogonal_factors(n, b, tw):
+    band = inputs.band_normal(n, b, seed=21)
+    A = band_to_dense(band, n, b)
+    d, e, U, V = oracle.reduce(band, n, b, tw, want_uv=True)
+    I = np.eye(n)
+    assert np.linalg.norm(U.T @ U - I) <= 10 * n * EPS
+    assert np.linalg.norm(V.T @ V - I) <= 10 * n * EPS
+    B = _bidiag(d, e)
+    assert np.linalg.norm(U.T @ A @ V - B) <= 10 * n * EPS * np.linalg.norm(A)
+    # no reflector ever touches row 0 / column 0 from the left, or column 0 from the right
+    assert np.array_equal(U[:, 0], I[:, 0])
+    assert np.array_equal(V[:, 0], I[:, 0])
+
+
+@pytest.mark.parametrize("n,b,tw", [(50, 7, 3), (64, 32, 16), (20, 19, 4)])
+def test_closed_forms_first_row(n, b, tw):
+    band = inputs.band_normal(n, b, seed=31)
+    A = band_to_dense(band, n, b)
+    d, e = oracle.reduce(band, n, b, tw)
+    assert d[0] == A[0, 0]
+    assert abs(abs(e[0]) - np.linalg.norm(A[0, 1:])) <= 4 * EPS * np.linalg.norm(A[0, 1:])
+
+
+def test_n3_closed_form():
+    """n = 3, b = 2: one right reflector on columns 1..2 of row 0 and one left reflector.
+    With u = (a01, a02)/||(a01, a02)|| and M the trailing 2x2 block: |d1| = ||M u||,
+    |d1 d2| = |a11 a22|, and d1^2 + e1^2 + d2^2 = ||M||_F^2."""
+    for seed in range(5):
+        rng = np.random.default_rng(seed)
+        a = rng.standard_normal(6)
+        A = np.array([[a[0], a[1], a[2]], [0, a[3], a[4]], [0, 0, a[5]]])
+        band = dense_to_band(A, 2)
+        d, e = oracle.reduce(band, 3, 2, 1)
+        u = A[0, 1:] / np.linalg.norm(A[0, 1:])
+        M = A[1:, 1:]
+        d1 = np.linalg.norm(M @ u)
+        d2 = abs(a[3] * a[5]) / d1
+        e1 = math.sqrt(max(np.sum(M * M) - d1 * d1 - d2 * d2, 0.0))
+        assert d[0] == a[0]
+        assert abs(abs(e[0]) - np.linalg.norm(A[0, 1:])) <= 4 * EPS * np.linalg.norm(A[0, 1:])
+        assert abs(abs(d[1]) - d1) <= 16 * EPS * d1
+        assert abs(abs(d[2]) - d2) <= 16 * EPS * max(d2, 1e-300)
+        assert abs(abs(e[1]) - e1) <= 1e-7 * np.linalg.norm(M)
+
+
+@pytest.mark.parametrize("n,b,tw", [(30, 6, 2), (25, 8, 3), (40, 5, 4)])
+def test_bidiagonal_input_unchanged(n, b, tw):
+    rng = np.random.default_rng(5)
+    A = np.diag(rng.standard_normal(n)) + np.diag(rng.standard_normal(n - 1), 1)
+    band = dense_to_band(A, b)
+    d, e = oracle.reduce(band, n, b, tw)
+    assert np.array_equal(d, np.diag(A))
+    assert np.array_equal(e, np.diag(A, 1))
+
+
+def test_degenerate_sizes():
+    # n = 0
+    d, e = oracle.reduce(np.zeros((0, 4)), 0, 3, 2)
+    assert d.size == 0 and e.size == 0
+    # n = 1
+    d, e = oracle.reduce(np.array([[0.0, 0.0, 2.5]]), 1, 2, 1)
+    assert d.tolist() == [2.5] and e.size == 0
+    # b = 0: diagonal passes through
+    band = np.arange(1.0, 6.0).reshape(5, 1)
+    d, e = oracle.reduce(band, 5, 0, 4)
+    assert d.tolist() == [1, 2, 3, 4, 5] and e.tolist() == [0, 0, 0, 0]
+    # n = 2 with b = 1: already bidiagonal
+    band = np.array([[0.0, 1.0], [2.0, 3.0]])
+    d, e = oracle.reduce(band, 2, 1, 4)
+    assert d.tolist() == [1.0, 3.0] and e.tolist() == [2.0]
+    # b >= n is clamped to n - 1
+    n = 6
+    band = inputs.band_normal(n, 9, seed=1)
+    A = band_to_dense(band, n, 9)
+    d, e = oracle.reduce(band, n, 9, 2)
+    s = oracle.singular_values(d, e)
+    assert np.allclose(s, np.linalg.svd(A, compute_uv=False), atol=1e-13)
+
+
+def test_invalid_arguments():
+    with pytest.raises(ValueError):
+        oracle.reduce(np.zeros((4, 3)), 4, 2, 0)       # TW < 1
+    with pytest.raises(ValueError):
+        oracle.reduce(np.zeros((4, 2)), 4, 2, 1)       # ldband < b+1
+
+
+def _well_conditioned_band(n, b, seed):
+    band = inputs.band_normal(n, b, seed)
+    band[:, b] += 3.0 * math.sqrt(b + 1)   # dominant diagonal keeps B far from splitting
+    return band
+
+
+@pytest.mark.parametrize("n,b", [(40, 6), (64, 12), (80, 20)])
+def test_unique_up_to_sign_vs_golub_kahan(n, b):
+    band = _well_conditioned_band(n, b, seed=41)
+    A = band_to_dense(band, n, b)
+    dg, eg = golub_kahan_dense(A)
+    for tw in sorted({1, 2, 3, b - 1}):
+        d, e = oracle.reduce(band, n, b, tw)
+        nrm = np.linalg.norm(A)
+        assert np.max(np.abs(np.abs(d) - np.abs(dg))) <= 1e-12 * nrm
+        assert np.max(np.abs(np.abs(e) - np.abs(eg))) <= 1e-12 * nrm
+
+
+@pytest.mark.parametrize("n,b,tw", [(40, 8, 2), (45, 10, 4), (33, 6, 5), (50, 16, 16), (29, 5, 3)])
+def test_pipelined_order_is_bitwise_sequential(n, b, tw):
+    """Random interleavings allowed by the half-step lag rule H = (4, 3, 2) for
+    c = (1, 2, >=3) reproduce the sequential oracle bitwise."""
+    band = inputs.band_normal(n, b, seed=n * b)
+    d0, e0 = oracle.reduce(band, n, b, tw)
+    for seed in range(1, 9):
+        d, e = oracle.reduce_pipelined(band, n, b, tw, (4, 3, 2), seed)
+        assert np.array_equal(d, d0) and np.array_equal(e, e0)
+
+
+def test_pipelined_detects_unsafe_rule():
+    """Planted mistake: a lag one half-step too short must change the result for some order."""
+    n, b, tw = 40, 8, 2   # c = 6 >= 3, safe lag 2, unsafe lag 1
+    band = inputs.band_normal(n, b, seed=9)
+    d0, e0 = oracle.reduce(band, n, b, tw)
+    differs = False
+    for seed in range(1, 30):
+        d, e = oracle.reduce_pipelined(band, n, b, tw, (4, 3, 1), seed)
+        if not (np.array_equal(d, d0) and np.array_equal(e, e0)):
+            differs = True
+            break
+    assert differs
