@@ -134,15 +134,37 @@ def _hypot2(a, b):
     return w * math.sqrt(1.0 + q * q)
 
 
+_SAFMIN = 2.2250738585072014e-308 / 2.220446049250313e-16
+
+
 def _house(x):
+    """LAPACK xLARFG, including its rescaling when |beta| < safmin."""
+    x = list(x)
     alpha = x[0]
     xn = _nrm2(x[1:])
     if xn == 0.0:
         return [1.0] + [0.0] * (len(x) - 1), 0.0, alpha
     h = _hypot2(alpha, xn)
     beta = -h if alpha >= 0.0 else h
+    knt = 0
+    if abs(beta) < _SAFMIN:
+        rs = 1.0 / _SAFMIN
+        while True:
+            knt += 1
+            x[1:] = [t * rs for t in x[1:]]
+            beta = beta * rs
+            alpha = alpha * rs
+            if not (abs(beta) < _SAFMIN and knt < 20):
+                break
+        xn = _nrm2(x[1:])
+        h = _hypot2(alpha, xn)
+        beta = -h if alpha >= 0.0 else h
     scal = 1.0 / (alpha - beta)
-    return [1.0] + [t * scal for t in x[1:]], (beta - alpha) / beta, beta
+    tau = (beta - alpha) / beta
+    v = [1.0] + [t * scal for t in x[1:]]
+    for _ in range(knt):
+        beta = beta * _SAFMIN
+    return v, tau, beta
 
 
 def stage_plan(b: int, tw_max: int):

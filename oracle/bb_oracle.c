@@ -81,8 +81,13 @@ static double hypot2(double a, double b) {
     return w * sqrt(1.0 + q * q);
 }
 
-/* Householder generation: x[0..m] in, v[0..m], *tau, *beta out. */
-static void house(const double *x, int64_t m, double *v, double *tau, double *beta) {
+/* Householder generation (LAPACK xLARFG): x[0..m] in, v[0..m], *tau, *beta out.
+ * When |beta| falls below safmin = DBL_MIN / DBL_EPSILON, x is rescaled by
+ * 1/safmin (at most 20 times) before tau and v are formed, so that 1/(alpha -
+ * beta) cannot overflow; beta is scaled back at the end. */
+static void house(const double *x_in, int64_t m, double *v, double *tau, double *beta) {
+    double x[BBO_MAXTW + 1];
+    for (int64_t t = 0; t <= m; ++t) x[t] = x_in[t];
     double alpha = x[0];
     double xn = nrm2(x + 1, m);
     v[0] = 1.0;
@@ -94,9 +99,24 @@ static void house(const double *x, int64_t m, double *v, double *tau, double *be
     }
     double h = hypot2(alpha, xn);
     double bt = (alpha >= 0.0) ? -h : h;
+    const double safmin = 2.2250738585072014e-308 / 2.220446049250313e-16;
+    const double rsafmn = 1.0 / safmin;
+    int knt = 0;
+    if (fabs(bt) < safmin) {
+        do {
+            ++knt;
+            for (int64_t t = 1; t <= m; ++t) x[t] = x[t] * rsafmn;
+            bt = bt * rsafmn;
+            alpha = alpha * rsafmn;
+        } while (fabs(bt) < safmin && knt < 20);
+        xn = nrm2(x + 1, m);
+        h = hypot2(alpha, xn);
+        bt = (alpha >= 0.0) ? -h : h;
+    }
     double scal = 1.0 / (alpha - bt);
     for (int64_t t = 1; t <= m; ++t) v[t] = x[t] * scal;
     *tau = (bt - alpha) / bt;
+    for (int k = 0; k < knt; ++k) bt = bt * safmin;
     *beta = bt;
 }
 
