@@ -110,19 +110,41 @@ def reduce_pipelined(band: np.ndarray, n: int, b: int, tw: int, lag, seed: int):
 # no fused multiply-add), same Householder convention and the same step order.
 # ----------------------------------------------------------------------------
 
+_TSML, _TBIG, _SSML, _SBIG = 2.0 ** -511, 2.0 ** 486, 2.0 ** 537, 2.0 ** -538
+
+
 def _nrm2(xs):
-    scale, ssq = 0.0, 1.0
+    """Reference LAPACK (>= 3.10) xNRM2: Blue's algorithm, Anderson's constants."""
+    notbig = True
+    asml = amed = abig = 0.0
     for x in xs:
-        if x != 0.0:
-            ax = abs(x)
-            if scale < ax:
-                q = scale / ax
-                ssq = 1.0 + ssq * (q * q)
-                scale = ax
-            else:
-                q = ax / scale
-                ssq = ssq + q * q
-    return scale * math.sqrt(ssq)
+        ax = abs(x)
+        if ax > _TBIG:
+            y = ax * _SBIG
+            abig = abig + y * y
+            notbig = False
+        elif ax < _TSML:
+            if notbig:
+                y = ax * _SSML
+                asml = asml + y * y
+        else:
+            amed = amed + ax * ax
+    if abig > 0.0:
+        if amed > 0.0 or amed != amed:
+            abig = abig + (amed * _SBIG) * _SBIG
+        scl, sumsq = 1.0 / _SBIG, abig
+    elif asml > 0.0:
+        if amed > 0.0 or amed != amed:
+            amed = math.sqrt(amed)
+            asml = math.sqrt(asml) / _SSML
+            ymin, ymax = (amed, asml) if asml > amed else (asml, amed)
+            q = ymin / ymax
+            scl, sumsq = 1.0, ymax * ymax * (1.0 + q * q)
+        else:
+            scl, sumsq = 1.0 / _SSML, asml
+    else:
+        scl, sumsq = 1.0, amed
+    return scl * math.sqrt(sumsq)
 
 
 def _hypot2(a, b):

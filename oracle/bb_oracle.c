@@ -53,23 +53,48 @@ static inline double *at(const bbo_band *B, int64_t i, int64_t q) {
     return &B->w[(i - q + B->uo) + q * B->ldw];
 }
 
-/* Euclidean norm by the classic scaled sum of squares (reference BLAS xNRM2). */
+/* Euclidean norm, reference LAPACK (>= 3.10) xNRM2: Blue's algorithm with the
+ * safe-scaling constants of Anderson (ACM TOMS Alg. 978).  Mid-range entries
+ * are summed as plain squares left to right; tiny and huge entries go to
+ * separately scaled accumulators that are combined at the end. */
 static double nrm2(const double *x, int64_t len) {
-    double scale = 0.0, ssq = 1.0;
+    const double tsml = 0x1p-511, tbig = 0x1p486, ssml = 0x1p537, sbig = 0x1p-538;
+    int notbig = 1;
+    double asml = 0.0, amed = 0.0, abig = 0.0;
     for (int64_t t = 0; t < len; ++t) {
-        if (x[t] != 0.0) {
-            double ax = fabs(x[t]);
-            if (scale < ax) {
-                double q = scale / ax;
-                ssq = 1.0 + ssq * (q * q);
-                scale = ax;
-            } else {
-                double q = ax / scale;
-                ssq = ssq + q * q;
-            }
+        double ax = fabs(x[t]);
+        if (ax > tbig) {
+            double y = ax * sbig;
+            abig = abig + y * y;
+            notbig = 0;
+        } else if (ax < tsml) {
+            if (notbig) { double y = ax * ssml; asml = asml + y * y; }
+        } else {
+            amed = amed + ax * ax;
         }
     }
-    return scale * sqrt(ssq);
+    double scl, sumsq;
+    if (abig > 0.0) {
+        if (amed > 0.0 || amed != amed) abig = abig + (amed * sbig) * sbig;
+        scl = 1.0 / sbig;
+        sumsq = abig;
+    } else if (asml > 0.0) {
+        if (amed > 0.0 || amed != amed) {
+            amed = sqrt(amed);
+            asml = sqrt(asml) / ssml;
+            double ymin = asml > amed ? amed : asml, ymax = asml > amed ? asml : amed;
+            double q = ymin / ymax;
+            scl = 1.0;
+            sumsq = ymax * ymax * (1.0 + q * q);
+        } else {
+            scl = 1.0 / ssml;
+            sumsq = asml;
+        }
+    } else {
+        scl = 1.0;
+        sumsq = amed;
+    }
+    return scl * sqrt(sumsq);
 }
 
 /* sqrt(a^2 + b^2) without avoidable overflow (LAPACK xLAPY2). */

@@ -234,3 +234,17 @@ def test_long_band_stays_finite():
     assert np.isfinite(d).all() and np.isfinite(e).all()
     A2 = np.sum(band * band)
     assert abs(np.sum(d * d) + np.sum(e * e) - A2) <= 100 * n * EPS * A2
+
+
+@pytest.mark.parametrize("scale", [1.0, 1e-300, 1e300, 2.0 ** -540, 2.0 ** 500])
+def test_nrm2_safe_scaling_matches_definition(scale):
+    """The norm used by the reflector generator (LAPACK >= 3.10 xNRM2) equals the
+    Euclidean norm within a few ulps in every magnitude regime, including mixed
+    tiny / mid / huge entries that go to different accumulators."""
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(33) * scale
+    exact = float(np.sqrt(np.sum((x / scale) ** 2))) * scale
+    assert abs(oracle._nrm2(x.tolist()) - exact) <= 8 * EPS * exact
+    mixed = [1e-310, 3.0, 1e-200, 4.0] if scale == 1.0 else [scale, 1e-320, 2.0 * scale]
+    ref = math.sqrt(sum((v / max(mixed)) ** 2 for v in mixed)) * max(mixed)
+    assert abs(oracle._nrm2(mixed) - ref) <= 8 * EPS * ref
