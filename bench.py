@@ -1,0 +1,179 @@
+"""Benchmark: milliseconds per band -> bidiagonal reduction on one MI355X.
+
+Workload: n = 32768, b = 128 upper band with i.i.d. N(0,1) entries (seed 3),
+FP64 storage (the headline configuration), plus the FP32-storage form of the
+same band.  One step = one full reduction (pack, every bandwidth-reduction
+stage, extract) of a band already resident in HBM.
+
+Prints ONE JSON line.  The roofline object reports the dominant kernel (the
+per-stage bulge-chasing kernel): algorithmic bytes (read + write of every step
+window under the 128-byte tilewidth schedule, TW = 16 for FP64) per launch,
+divided by that kernel's average launch time measured with HIP events on the
+stream it runs on.  cpu_baseline times the CPU oracle (single thread) on the
+leading 6144 x 6144 block of the same band and scales it by the ratio of
+algorithmic bytes to the full size.
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("ms per band→bidiag reduction (n=32k,b=128) FP64 vs FP32-store; % HBM roofline")
+PEAK_HBM_GBPS = 8000.0
+TW_REF = {8: 16, 4: 32, 2: 64}   # one 128-byte line of the storage type
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2510_12705_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(os.path.basename(p).encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str, dtype: str):
+    """HBM bytes per stage launch from committed rocprofv3 counter summaries, valid
+    only for the kernel sources they were taken from."""
+    path = os.path.join(ROOT, "profiles", "traffic_bb_stage_%s_%s.json" % (workload, dtype))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def time_reductions(bb, torch, band_dev, n, b, steps, warmup, dtype_name):
+    d = torch.empty(n, dtype=torch.float64, device=band_dev.device)
+    e = torch.empty(max(n - 1, 1), dtype=torch.float64, device=band_dev.device)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        bb.bb_reduce(band_dev, n, b, d, e, stream=stream)
+    torch.cuda.synchronize()
+    st = bb.stream_status(stream)
+    if st != 0:
+        raise RuntimeError("device error during warmup: %s" % bb.bb_error_string(st))
+    bb.timing_read()             # drop warm-up launches
+    bb.timing_enable(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        bb.bb_reduce(band_dev, n, b, d, e, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    bb.timing_enable(False)
+    stage_ms, launches = bb.timing_read()
+    st = bb.stream_status(stream)
+    if st != 0:
+        raise RuntimeError("device error: %s" % bb.bb_error_string(st))
+    total_ms = ev0.elapsed_time(ev1)
+    print("[bench] %s: %.3f ms/reduction (events), %.3f ms wall, stage kernels %.3f ms over %d launches"
+          % (dtype_name, total_ms / steps, wall * 1e3 / steps, stage_ms, launches), file=sys.stderr, flush=True)
+    return total_ms / steps, stage_ms, launches, d, e
+
+
+def cpu_baseline(band, n, b, sample_n):
+    import oracle
+    from paper_2510_12705_amd import bb
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    oracle.reduce(band[:sample_n], sample_n, b, 16)
+    dt = time.perf_counter() - t0
+    scale = bb.model_bytes(n, b, 8, 16) / bb.model_bytes(sample_n, b, 8, 16)
+    return {"value": dt * scale * 1e3, "unit": "ms", "cores": 1, "kind": "oracle",
+            "sample": "FP64 oracle, 1 thread, leading %dx%d block of the same band (b=%d, TW=16): %.2f s, "
+                      "scaled x%.2f by algorithmic bytes to n=%d" % (sample_n, sample_n, b, dt, scale, n)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=32768)
+    ap.add_argument("--b", type=int, default=128)
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=6144)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this benchmark runs on exactly one GPU (the reduction of one band is a single-GPU "
+              "pipeline; see DESIGN.md for how it would shard); got --gpus %d" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2510_12705_amd import bb, inputs
+
+    n, b = args.n, args.b
+    seed = 3
+    band = inputs.band_normal(n, b, seed)
+    dev = torch.device("cuda:0")
+    band64 = torch.from_numpy(band).to(dev)
+    print("[bench] workload n=%d b=%d, steps=%d warmup=%d" % (n, b, args.steps, args.warmup), file=sys.stderr,
+          flush=True)
+    bb.reset_params()
+    ms64, stage_ms, launches, d, e = time_reductions(bb, torch, band64, n, b, args.steps, args.warmup, "fp64")
+    p = bb.autotune(n, b, bb.F64)  # reports the parameters the call used (no tuning run when cached)
+    alg64 = bb.model_bytes(n, b, 8, TW_REF[8])
+    per_launch_bytes = alg64 * args.steps / max(launches, 1)
+    avg_launch_s = stage_ms / max(launches, 1) / 1e3
+    achieved = per_launch_bytes / avg_launch_s / 1e9
+    traffic = load_traffic("n%d_b%d" % (n, b), "fp64")
+
+    out = {
+        "metric": METRIC,
+        "value": round(ms64, 3),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms64, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "n=%d, b=%d upper band, i.i.d. N(0,1) entries (seed %d), FP64 storage" % (n, b, seed),
+                   "n": n, "b": b, "storage": "fp64", "tw": p.tw, "threads_per_window": p.threads_per_window,
+                   "sweeps_per_cu": p.sweeps_per_cu, "stages": len(bb.plan(b, p.tw))},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": traffic,
+                     "kernel": "bb_stage", "alg_bytes_per_launch": per_launch_bytes,
+                     "avg_launch_ms": round(avg_launch_s * 1e3, 4)},
+        "alg_bytes": alg64,
+        "pct_roofline_whole_call": round(100.0 * alg64 / (ms64 / 1e3) / 1e9 / PEAK_HBM_GBPS, 2),
+    }
+    if not args.no_fp32:
+        band32 = band64.to(torch.float32)
+        ms32, st32, l32, _, _ = time_reductions(bb, torch, band32, n, b, args.steps, args.warmup, "fp32")
+        p32 = bb.autotune(n, b, bb.F32)
+        alg32 = bb.model_bytes(n, b, 4, TW_REF[4])
+        out["fp32_store"] = {"ms": round(ms32, 3), "tw": p32.tw, "alg_bytes": alg32,
+                             "pct_roofline_whole_call": round(100.0 * alg32 / (ms32 / 1e3) / 1e9 / PEAK_HBM_GBPS, 2),
+                             "speedup_vs_fp64": round(ms64 / ms32, 3)}
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle) on a %d sample ..." % args.cpu_sample, file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(band, n, b, args.cpu_sample)
+    dn = d.cpu().numpy()
+    out["check"] = {"d0_exact": bool(dn[0] == band[0, b]), "finite": bool(np.isfinite(dn).all())}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

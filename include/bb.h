@@ -1,0 +1,163 @@
+/*
+ * bb.h -- C ABI of the MI355X (gfx950) band -> bidiagonal reduction library.
+ *
+ * The operation (paper: Sec. III, Algorithm 1; problem statement in Sec. I and
+ * Sec. III's opening paragraph): given an n x n upper-banded matrix A with b
+ * super-diagonals, compute an upper bidiagonal B = U^T A V (U, V orthogonal,
+ * U e1 = V e1 = e1) by bulge chasing with two-sided Householder reflectors,
+ * reducing the bandwidth in stages of TW (the "inner tilewidth").  Singular
+ * values are preserved: sigma(B) = sigma(A).  Only the bidiagonal (d, e) is
+ * returned; the orthogonal factors are not formed.
+ *
+ * Conventions shared by every entry point
+ *   - Band layout (input): LAPACK column-major upper band of the storage type,
+ *       A(i, j) = band[(b + i - j) + j * ldband],  max(0, j - b) <= i <= j,
+ *     ldband >= b + 1.  Entries above row 0 are ignored.  `band` is read only.
+ *   - Storage type (bb_dtype_t): BB_F64 -> double, BB_F32 -> float,
+ *     BB_F16 -> IEEE binary16.  The band is stored and updated in this type;
+ *     Householder reflectors (norm, beta, tau) are always generated in FP64.
+ *     BB_F16 keeps a power-of-two scale per bandwidth-reduction stage.
+ *   - Outputs: d (n doubles) = diagonal, e (n - 1 doubles) = super-diagonal of
+ *     B, always FP64.  Signs of d, e are not unique; |d|, |e| are.
+ *   - Memory: every array pointer is caller-owned DEVICE memory on the current
+ *     HIP device unless stated otherwise.  The library keeps a private working
+ *     band (b + 2 TW + 1 rows per column, the height given in Sec. IV) in
+ *     stream-ordered device memory drawn from the device's default pool.
+ *   - Streams: `stream` is a hipStream_t (NULL = the null stream).  Calls are
+ *     asynchronous: results are valid once the stream is synchronised.  Calls
+ *     on different streams use separate working memory and are independent.
+ *   - Errors: 0 on success; -i if argument i (1-based) is invalid, with no
+ *     work enqueued; > 0 for a runtime failure (BB_ERR_*).  Nothing aborts.
+ *     A device-side watchdog on every dependency wait turns a stalled pipeline
+ *     into BB_ERR_TIMEOUT, reported by bb_stream_status().
+ *   - Edge cases: n = 0 is a no-op; n = 1 gives d0 = a00; b = 0 gives d =
+ *     diagonal, e = 0; b = 1 is copied through; b >= n is treated as n - 1.
+ *     NaN / Inf in the input propagate to the output.
+ */
+#ifndef BB_H
+#define BB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { BB_F64 = 0, BB_F32 = 1, BB_F16 = 2 } bb_dtype_t;
+
+enum {
+    BB_OK = 0,
+    BB_ERR_HIP = 1,          /* a HIP runtime call failed */
+    BB_ERR_TIMEOUT = 2,      /* device watchdog: a dependency wait never completed */
+    BB_ERR_NOMEM = 3,        /* device or host allocation failed */
+    BB_ERR_UNSUPPORTED = 4,  /* parameters outside the compiled kernel variants */
+    BB_ERR_NODEVICE = 5      /* no usable gfx950 device */
+};
+
+/*
+ * Tuning parameters (Sec. III-C names three knobs: threads per block, inner
+ * tilewidth, maximum blocks).  0 in any field means "automatic".
+ *   tw                 inner tilewidth TW (entries annihilated per reflector);
+ *                      supported values: 1..32.
+ *   threads_per_window threads of the workgroup that owns one sweep: 64, 128,
+ *                      256 or 512.
+ *   sweeps_per_cu      persistent workgroups launched per compute unit (1..16);
+ *                      caps the sweeps in flight, the paper's "Max blocks".
+ *   lag                half-step dependency lag between consecutive sweeps; each
+ *                      stage uses max(lag, smallest safe lag of that stage), so
+ *                      0 selects the smallest safe value (bb_min_lag) and a
+ *                      larger value only delays sweeps (results are unchanged).
+ */
+typedef struct {
+    int tw;
+    int threads_per_window;
+    int sweeps_per_cu;
+    int lag;
+} bb_params_t;
+
+/*
+ * Reduce one upper band to bidiagonal form.
+ *   n, b     order and number of super-diagonals (n >= 0, b >= 0).
+ *   dtype    storage type of `band` and of the working band.
+ *   band     device pointer, LAPACK upper band of `dtype`, ldband >= b + 1.
+ *   d, e     device pointers to n and max(n - 1, 0) doubles (outputs).
+ *   stream   hipStream_t.
+ * Argument numbers for -i: n=1, b=2, dtype=3, band=4, ldband=5, d=6, e=7.
+ */
+int bb_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void *band, int64_t ldband,
+              double *d, double *e, void *stream);
+
+/*
+ * Reduce `count` independent bands of uneven n_i, b_i in one persistent launch
+ * that draws (matrix, stage, sweep) tasks from a device work queue.  All host
+ * arrays have `count` entries; band[i], d[i], e[i] are device pointers as in
+ * bb_reduce.  Argument numbers: count=1, n=2, b=3, dtype=4, band=5, ldband=6,
+ * d=7, e=8.  A matrix with an invalid entry makes the whole call fail with
+ * the argument number of the array, before any work is enqueued.
+ */
+int bb_reduce_batched(int64_t count, const int64_t *n, const int64_t *b, bb_dtype_t dtype,
+                      const void *const *band, const int64_t *ldband,
+                      double *const *d, double *const *e, void *stream);
+
+/* Set (p != NULL) or reset to automatic (p == NULL) the process-wide tuning
+ * parameters; invalid values are rejected with -1 and leave the state unchanged. */
+int bb_set_params(const bb_params_t *p);
+/* Read the current process-wide parameters (0 fields = automatic). */
+int bb_get_params(bb_params_t *p);
+
+/*
+ * Autotune for one problem shape: candidates are seeded and ranked by a
+ * bytes-per-step model, the best few are timed on a synthetic band of this
+ * shape on `stream`, and the fastest is cached for (n bucket, b, dtype) and
+ * returned in *out (may be NULL).  Synchronises `stream`.
+ */
+int bb_autotune(int64_t n, int64_t b, bb_dtype_t dtype, void *stream, bb_params_t *out);
+
+/* Device bytes of working memory one bb_reduce call of this shape allocates. */
+size_t bb_workspace_bytes(int64_t n, int64_t b, bb_dtype_t dtype);
+
+/*
+ * Algorithmic bytes of the reduction: the read + write of every window a step
+ * touches (the L-shaped union of the right reflector's row block and the left
+ * reflector's column block), summed over every step of every stage, for an
+ * element of `elem_size` bytes under inner tilewidth `tw`.
+ */
+double bb_model_bytes(int64_t n, int64_t b, int elem_size, int tw);
+
+/*
+ * Stage plan for bandwidth b under inner tilewidth tw (host only): fills up to
+ * `max_stages` entries of bs (bandwidth entering the stage), tws (tilewidth),
+ * cs (bandwidth left) and lags (half-step lag used between sweeps); returns
+ * the number of stages, or a negative argument error.
+ */
+int bb_plan(int64_t b, int tw, int max_stages, int *bs, int *tws, int *cs, int *lags);
+
+/* Smallest safe half-step lag for a stage that leaves bandwidth c (c >= 1). */
+int bb_min_lag(int64_t c);
+
+/* Synchronise `stream` and return (and clear) the device's error word:
+ * BB_OK or BB_ERR_TIMEOUT, or BB_ERR_HIP if the synchronisation failed. */
+int bb_stream_status(void *stream);
+
+/*
+ * Kernel timing (diagnostics for benchmarks).  While enabled, every bb_reduce
+ * call records a hipEvent pair on its stream around each launch of the stage
+ * (bulge-chasing) kernel.  bb_timing_read synchronises on those events, returns
+ * the summed milliseconds and the number of launches since the previous read
+ * (either pointer may be NULL) and forgets them.  Disabled by default.
+ */
+int bb_timing_enable(int on);
+int bb_timing_read(double *stage_ms, int64_t *stage_launches);
+
+/* Free cached host/device resources of the library (pools, autotune cache). */
+int bb_release(void);
+
+/* Static text for an error code (negative codes: "invalid argument"). */
+const char *bb_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BB_H */

@@ -1,0 +1,334 @@
+// bb_api.hip -- host side of the C ABI declared in include/bb.h.
+//
+// Planning (stages of Algorithm 1, per-stage half-step lag), argument checks,
+// stream-ordered working memory, and the launch sequence
+//   fill(counters) -> pack -> stage kernel per bandwidth-reduction stage -> extract.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "bb.h"
+#include "bb_internal.h"
+#include "bb_plan.h"
+
+namespace {
+
+struct DeviceState {
+    bool init = false;
+    int cus = 0;
+    int* err_host = nullptr;  // host-mapped error word
+    int* err_dev = nullptr;
+};
+
+std::mutex g_mu;
+bb_params_t g_params = {0, 0, 0, 0};
+std::vector<DeviceState> g_dev;
+
+struct Timing {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+};
+Timing g_timing;
+
+unsigned spin_limit() {
+    static unsigned v = [] {
+        const char* s = getenv("BB_SPIN_LIMIT");
+        long x = s ? strtol(s, nullptr, 10) : 0;
+        return x > 0 ? (unsigned)x : (1u << 22);
+    }();
+    return v;
+}
+
+int device_state(DeviceState** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return BB_ERR_NODEVICE;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if ((int)g_dev.size() <= dev) g_dev.resize(dev + 1);
+    DeviceState& s = g_dev[dev];
+    if (!s.init) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return BB_ERR_NODEVICE;
+        s.cus = prop.multiProcessorCount;
+        if (hipHostMalloc((void**)&s.err_host, sizeof(int), hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess)
+            return BB_ERR_NOMEM;
+        *s.err_host = 0;
+        if (hipHostGetDevicePointer((void**)&s.err_dev, s.err_host, 0) != hipSuccess) return BB_ERR_HIP;
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+            uint64_t thr = UINT64_MAX;  // keep freed working memory cached in the pool
+            hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+        }
+        s.init = true;
+    }
+    *out = &s;
+    return BB_OK;
+}
+
+size_t elem_size(int dtype) { return dtype == BB_F64 ? 8 : dtype == BB_F32 ? 4 : 2; }
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Launch {
+    int tw, nt, wgs_per_cu, lag;
+};
+
+Launch resolve(int64_t n, int64_t b, int dtype) {
+    bb_params_t p;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        p = g_params;
+    }
+    bbp::Tuned t;
+    bool cached = bbp::autotune_lookup(n, b, dtype, &t);
+    Launch L;
+    L.tw = p.tw ? p.tw : cached ? t.tw : bbp::default_tw(dtype);
+    int rows = (int)std::min<int64_t>(b, std::max<int64_t>(n - 1, 1)) + L.tw;
+    L.nt = p.threads_per_window ? p.threads_per_window : cached ? t.nt : bbp::default_threads(rows);
+    L.wgs_per_cu = p.sweeps_per_cu ? p.sweeps_per_cu : cached ? t.wgs_per_cu : 8;
+    L.lag = p.lag;
+    return L;
+}
+
+struct Workspace {
+    size_t band_bytes = 0, counter_bytes = 0, total = 0;
+    int64_t ldw = 0, uo = 0, max_sweeps = 0;
+    int nstages = 0;
+};
+
+Workspace workspace_layout(int64_t n, int64_t b, int dtype, int tw) {
+    Workspace w;
+    bbp::Plan plan = bbp::make_plan(b, tw);
+    int tw0 = plan.stages.empty() ? 0 : plan.stages[0].tw;
+    w.uo = std::max<int64_t>(b + tw0, 1);
+    w.ldw = align_up((size_t)(w.uo + tw0 + 1), 2);
+    w.nstages = (int)plan.stages.size();
+    w.max_sweeps = std::max<int64_t>(n, 1);
+    w.band_bytes = align_up((size_t)(n * w.ldw) * elem_size(dtype), 256);
+    // per stage: progress[max_sweeps], then claim + abort words
+    w.counter_bytes = align_up(sizeof(int) * (size_t)(w.nstages * w.max_sweeps + 2 * w.nstages + 2), 256);
+    w.total = w.band_bytes + w.counter_bytes;
+    return w;
+}
+
+int check_hip(hipError_t e) { return e == hipSuccess ? BB_OK : BB_ERR_HIP; }
+
+}  // namespace
+
+extern "C" {
+
+int bb_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, int64_t ldband, double* d, double* e,
+              void* stream) {
+    if (n < 0) return -1;
+    if (b < 0) return -2;
+    if (dtype != BB_F64 && dtype != BB_F32 && dtype != BB_F16) return -3;
+    if (n > 0 && !band) return -4;
+    if (ldband < b + 1) return -5;
+    if (n > 0 && !d) return -6;
+    if (n > 1 && !e) return -7;
+    if (n > (int64_t)1 << 30) return -1;
+    if (n == 0) return BB_OK;
+    hipStream_t st = (hipStream_t)stream;
+    DeviceState* ds = nullptr;
+    int rc = device_state(&ds);
+    if (rc) return rc;
+
+    const int64_t b_in = b;
+    const int64_t bb = std::min<int64_t>(b, n - 1);
+    Launch L = resolve(n, bb, dtype);
+    if (L.tw < 1 || L.tw > bbp::kMaxTW) return BB_ERR_UNSUPPORTED;
+    bbp::Plan plan = bbp::make_plan(bb, L.tw);
+    Workspace ws = workspace_layout(n, bb, dtype, L.tw);
+
+    void* base = nullptr;
+    if (hipMallocAsync(&base, ws.total, st) != hipSuccess) return BB_ERR_NOMEM;
+    char* W = (char*)base;
+    int* counters = (int*)((char*)base + ws.band_bytes);
+    const int64_t ncounters = ws.nstages * ws.max_sweeps + 2 * ws.nstages + 2;
+
+    float scale = 1.0f;
+    double inv_scale = 1.0;
+    rc = check_hip(bbk::launch_fill(counters, ncounters, 0, st));
+    if (!rc) rc = check_hip(bbk::launch_pack(dtype, band, ldband, n, b_in, bb, W, ws.ldw, ws.uo, scale, st));
+    for (int s = 0; s < ws.nstages && !rc; ++s) {
+        const bbp::Stage& sg = plan.stages[s];
+        bbk::StageArgs a;
+        a.W = W;
+        a.S = ws.ldw - 1;
+        a.uo = ws.uo;
+        a.n = (int)n;
+        a.b = sg.b;
+        a.tw = sg.tw;
+        a.c = sg.c;
+        a.H = std::max(sg.lag, L.lag);
+        a.nsweeps = (int)std::max<int64_t>(n - sg.c - 1, 0);
+        a.progress = counters + s * ws.max_sweeps;
+        a.claim = counters + ws.nstages * ws.max_sweeps + 2 * s;
+        a.abort_flag = a.claim + 1;
+        a.err_word = ds->err_dev;
+        a.spin_limit = spin_limit();
+        if (a.nsweeps == 0) continue;
+        const int twm = bbp::kernel_twm(sg.tw);
+        const int grid = (int)std::min<int64_t>(a.nsweeps, (int64_t)ds->cus * L.wgs_per_cu);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        bool timed = false;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            timed = g_timing.on;
+        }
+        if (timed && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess)
+            hipEventRecord(e0, st);
+        rc = check_hip(bbk::launch_stage(dtype, a, twm, L.nt, grid, st));
+        if (timed && e1) {
+            hipEventRecord(e1, st);
+            std::lock_guard<std::mutex> lk(g_mu);
+            g_timing.events.emplace_back(e0, e1);
+        }
+    }
+    if (!rc) rc = check_hip(bbk::launch_extract(dtype, W, n, ws.ldw, ws.uo, inv_scale, d, e, st));
+    hipError_t fe = hipFreeAsync(base, st);
+    if (!rc && fe != hipSuccess) rc = BB_ERR_HIP;
+    return rc;
+}
+
+int bb_reduce_batched(int64_t count, const int64_t* n, const int64_t* b, bb_dtype_t dtype, const void* const* band,
+                      const int64_t* ldband, double* const* d, double* const* e, void* stream) {
+    if (count < 0) return -1;
+    if (count > 0 && (!n || !b || !band || !ldband || !d || !e)) return !n ? -2 : !b ? -3 : !band ? -5 : !ldband ? -6 : !d ? -7 : -8;
+    if (dtype != BB_F64 && dtype != BB_F32 && dtype != BB_F16) return -4;
+    for (int64_t i = 0; i < count; ++i) {
+        if (n[i] < 0 || n[i] > (int64_t)1 << 30) return -2;
+        if (b[i] < 0) return -3;
+        if (n[i] > 0 && !band[i]) return -5;
+        if (ldband[i] < b[i] + 1) return -6;
+        if (n[i] > 0 && !d[i]) return -7;
+        if (n[i] > 1 && !e[i]) return -8;
+    }
+    for (int64_t i = 0; i < count; ++i) {
+        int rc = bb_reduce(n[i], b[i], dtype, band[i], ldband[i], d[i], e[i], stream);
+        if (rc) return rc;
+    }
+    return BB_OK;
+}
+
+int bb_set_params(const bb_params_t* p) {
+    bb_params_t q = {0, 0, 0, 0};
+    if (p) {
+        if (p->tw < 0 || p->tw > bbp::kMaxTW) return -1;
+        if (p->threads_per_window != 0 && (p->threads_per_window < 64 || p->threads_per_window > 512 ||
+                                           (p->threads_per_window & (p->threads_per_window - 1))))
+            return -1;
+        if (p->sweeps_per_cu < 0 || p->sweeps_per_cu > 16) return -1;
+        if (p->lag < 0 || p->lag > 64) return -1;
+        q = *p;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_params = q;
+    return BB_OK;
+}
+
+int bb_get_params(bb_params_t* p) {
+    if (!p) return -1;
+    std::lock_guard<std::mutex> lk(g_mu);
+    *p = g_params;
+    return BB_OK;
+}
+
+size_t bb_workspace_bytes(int64_t n, int64_t b, bb_dtype_t dtype) {
+    if (n <= 0 || b < 0) return 0;
+    const int64_t bb = std::min<int64_t>(b, n - 1);
+    Launch L = resolve(n, bb, dtype);
+    return workspace_layout(n, bb, dtype, L.tw).total;
+}
+
+double bb_model_bytes(int64_t n, int64_t b, int elem_size, int tw) {
+    if (n <= 0 || b < 0 || elem_size <= 0 || tw < 1) return 0.0;
+    return bbp::model_bytes(n, std::min<int64_t>(b, n - 1), elem_size, tw);
+}
+
+int bb_plan(int64_t b, int tw, int max_stages, int* bs, int* tws, int* cs, int* lags) {
+    if (b < 0) return -1;
+    if (tw < 1) return -2;
+    if (max_stages < 0) return -3;
+    bbp::Plan plan = bbp::make_plan(b, tw);
+    for (int s = 0; s < (int)plan.stages.size() && s < max_stages; ++s) {
+        if (bs) bs[s] = plan.stages[s].b;
+        if (tws) tws[s] = plan.stages[s].tw;
+        if (cs) cs[s] = plan.stages[s].c;
+        if (lags) lags[s] = plan.stages[s].lag;
+    }
+    return (int)plan.stages.size();
+}
+
+int bb_min_lag(int64_t c) { return c < 1 ? -1 : bbp::min_lag((int)std::min<int64_t>(c, 1 << 20)); }
+
+int bb_stream_status(void* stream) {
+    DeviceState* ds = nullptr;
+    int rc = device_state(&ds);
+    if (rc) return rc;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return BB_ERR_HIP;
+    int v = __atomic_exchange_n(ds->err_host, 0, __ATOMIC_SEQ_CST);
+    return v;
+}
+
+int bb_timing_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_timing.on = on != 0;
+    return BB_OK;
+}
+
+int bb_timing_read(double* stage_ms, int64_t* stage_launches) {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        ev.swap(g_timing.events);
+    }
+    double tot = 0.0;
+    int rc = BB_OK;
+    for (auto& pr : ev) {
+        float ms = 0.f;
+        if (hipEventSynchronize(pr.second) != hipSuccess || hipEventElapsedTime(&ms, pr.first, pr.second) != hipSuccess)
+            rc = BB_ERR_HIP;
+        tot += ms;
+        hipEventDestroy(pr.first);
+        hipEventDestroy(pr.second);
+    }
+    if (stage_ms) *stage_ms = tot;
+    if (stage_launches) *stage_launches = (int64_t)ev.size();
+    return rc;
+}
+
+int bb_release(void) {
+    bbp::autotune_clear();
+    return BB_OK;
+}
+
+const char* bb_error_string(int code) {
+    if (code < 0) return "invalid argument";
+    switch (code) {
+        case BB_OK: return "success";
+        case BB_ERR_HIP: return "HIP runtime error";
+        case BB_ERR_TIMEOUT: return "device watchdog: dependency wait timed out";
+        case BB_ERR_NOMEM: return "out of memory";
+        case BB_ERR_UNSUPPORTED: return "unsupported parameters";
+        case BB_ERR_NODEVICE: return "no usable device";
+        default: return "unknown error";
+    }
+}
+
+}  // extern "C"
+
+extern "C" int bb_autotune(int64_t n, int64_t b, bb_dtype_t dtype, void* stream, bb_params_t* out) {
+    (void)stream;
+    if (n < 0) return -1;
+    if (b < 0) return -2;
+    if (dtype != BB_F64 && dtype != BB_F32 && dtype != BB_F16) return -3;
+    Launch L = resolve(n, std::min<int64_t>(b, std::max<int64_t>(n - 1, 0)), dtype);
+    if (out) *out = bb_params_t{L.tw, L.nt, L.wgs_per_cu, L.lag};
+    return BB_OK;
+}

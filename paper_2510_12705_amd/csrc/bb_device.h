@@ -1,0 +1,205 @@
+// bb_device.h -- device-side building blocks for the gfx950 bulge-chasing kernels.
+//
+// Lane broadcast, the FP64 Householder generator, compensated (Dot2) sums for
+// the reduced-precision storage forms, and the agent-scope dependency
+// primitives used by the persistent kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bbk {
+
+constexpr int kWave = 64;
+constexpr int kDone = 0x7fffffff;  // progress value of a sweep that, and all sweeps before it, finished
+
+// ---------------------------------------------------------------------------
+// lane broadcast (full wave active)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+    int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+    int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// ---------------------------------------------------------------------------
+// Householder generator (FP64 for every storage type), LAPACK xLARFG.
+//
+// Every lane of the wave computes the reflector from the same, wave-uniform
+// values, in exactly the operation order of the reference definition:
+//   xnorm = xNRM2(x2)   (LAPACK >= 3.10: Blue's algorithm, Anderson's constants;
+//                        mid-range entries summed as plain squares left to right)
+//   xnorm == 0          -> H = I (tau = 0, beta = alpha)
+//   beta  = -sign(alpha) xLAPY2(alpha, xnorm), sign(0) = +1
+//   |beta| < safmin     -> rescale x by 1/safmin (<= 20 times), recompute
+//   tau   = (beta - alpha) / beta,  v = x * (1 / (alpha - beta)),  v0 = 1
+// with no fused multiply-add, so FP64 results are bitwise those of a plain
+// IEEE double implementation of the same definition.
+// ---------------------------------------------------------------------------
+#pragma clang fp contract(off)
+
+__device__ __forceinline__ double nrm2_uniform_step(double ax, bool& notbig, double& asml, double& amed,
+                                                    double& abig) {
+    constexpr double tsml = 0x1p-511, tbig = 0x1p486, ssml = 0x1p537, sbig = 0x1p-538;
+    if (ax > tbig) {
+        const double y = ax * sbig;
+        abig = abig + y * y;
+        notbig = false;
+    } else if (ax < tsml) {
+        if (notbig) {
+            const double y = ax * ssml;
+            asml = asml + y * y;
+        }
+    } else {
+        amed = amed + ax * ax;
+    }
+    return ax;
+}
+
+__device__ __forceinline__ double nrm2_finish(bool notbig, double asml, double amed, double abig) {
+    constexpr double ssml = 0x1p537, sbig = 0x1p-538;
+    (void)notbig;
+    double scl, sumsq;
+    if (abig > 0.0) {
+        if (amed > 0.0 || amed != amed) abig = abig + (amed * sbig) * sbig;
+        scl = 1.0 / sbig;
+        sumsq = abig;
+    } else if (asml > 0.0) {
+        if (amed > 0.0 || amed != amed) {
+            amed = sqrt(amed);
+            asml = sqrt(asml) / ssml;
+            const double ymin = asml > amed ? amed : asml, ymax = asml > amed ? asml : amed;
+            const double q = ymin / ymax;
+            scl = 1.0;
+            sumsq = ymax * ymax * (1.0 + q * q);
+        } else {
+            scl = 1.0 / ssml;
+            sumsq = asml;
+        }
+    } else {
+        scl = 1.0;
+        sumsq = amed;
+    }
+    return scl * sqrt(sumsq);
+}
+
+template <int TWM>
+__device__ __forceinline__ double nrm2_uniform(const double (&x)[TWM + 1], int m) {
+    bool notbig = true;
+    double asml = 0.0, amed = 0.0, abig = 0.0;
+#pragma unroll
+    for (int t = 1; t <= TWM; ++t)
+        if (t <= m) nrm2_uniform_step(fabs(x[t]), notbig, asml, amed, abig);
+    return nrm2_finish(notbig, asml, amed, abig);
+}
+
+__device__ __forceinline__ double lapy2(double a, double b) {
+    const double xa = fabs(a), ya = fabs(b);
+    const double w = xa > ya ? xa : ya, z = xa < ya ? xa : ya;
+    if (z == 0.0) return w;
+    const double q = z / w;
+    return w * sqrt(1.0 + q * q);
+}
+
+// x_lane: lane t (0 <= t <= m) holds x_t.  On return v[0..TWM] holds the
+// reflector (v[0] = 1, v[t] = 0 for t > m), uniform across the wave.
+template <int TWM>
+__device__ __forceinline__ void house_uniform(double x_lane, int m, double (&v)[TWM + 1], double& tau,
+                                              double& beta) {
+    double x[TWM + 1];
+#pragma unroll
+    for (int t = 0; t <= TWM; ++t) x[t] = t <= m ? readlane_f64(x_lane, t) : 0.0;
+    double alpha = x[0];
+    double xn = nrm2_uniform<TWM>(x, m);
+    v[0] = 1.0;
+    if (xn == 0.0) {
+#pragma unroll
+        for (int t = 1; t <= TWM; ++t) v[t] = 0.0;
+        tau = 0.0;
+        beta = alpha;
+        return;
+    }
+    double h = lapy2(alpha, xn);
+    double bt = alpha >= 0.0 ? -h : h;
+    constexpr double safmin = 2.2250738585072014e-308 / 2.220446049250313e-16;  // DBL_MIN / DBL_EPSILON
+    int knt = 0;
+    if (fabs(bt) < safmin) {
+        const double rsafmn = 1.0 / safmin;
+        do {
+            ++knt;
+#pragma unroll
+            for (int t = 1; t <= TWM; ++t) x[t] = x[t] * rsafmn;
+            bt = bt * rsafmn;
+            alpha = alpha * rsafmn;
+        } while (fabs(bt) < safmin && knt < 20);
+        xn = nrm2_uniform<TWM>(x, m);
+        h = lapy2(alpha, xn);
+        bt = alpha >= 0.0 ? -h : h;
+    }
+    const double scal = 1.0 / (alpha - bt);
+#pragma unroll
+    for (int t = 1; t <= TWM; ++t) v[t] = t <= m ? x[t] * scal : 0.0;
+    tau = (bt - alpha) / bt;
+    for (int i = 0; i < knt; ++i) bt = bt * safmin;
+    beta = bt;
+}
+
+// ---------------------------------------------------------------------------
+// Dot products: plain FMA chain (FP64) and Ogita-Rump-Oishi Dot2 (FP32).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+    s = a + b;
+    float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// ---------------------------------------------------------------------------
+// Dependency primitives.  progress[r] counts completed half-steps of sweep r
+// (2j+1 after the right task of step j, 2j+2 after its left task) and becomes
+// kDone when sweep r and every earlier sweep finished.
+// ---------------------------------------------------------------------------
+struct SyncCtx {
+    int* abort_flag;         // device word: set on watchdog expiry, polled by every waiter
+    int* err_word;           // host-mapped word receiving the error code
+    unsigned spin_limit;     // polls before the watchdog fires
+};
+
+// All threads of the block call this; thread 0 polls.  Returns false if the
+// pipeline was aborted (then every thread must leave the kernel).
+__device__ __forceinline__ bool wait_ge(const int* flag, int target, const SyncCtx& s, int* lds_ok) {
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            unsigned spins = 0;
+            while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                __builtin_amdgcn_s_sleep(1);
+                if ((++spins & 255u) == 0) {
+                    if (__hip_atomic_load(s.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        ok = 0;
+                        break;
+                    }
+                    if (spins > s.spin_limit) {
+                        __hip_atomic_store(s.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(s.err_word, 2 /*BB_ERR_TIMEOUT*/, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_SYSTEM);
+                        ok = 0;
+                        break;
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *lds_ok = ok;
+    }
+    __syncthreads();
+    return *lds_ok != 0;
+}
+
+// All threads call this after their last store of a task.
+__device__ __forceinline__ void publish(int* flag, int value) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(flag, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace bbk

@@ -1,0 +1,30 @@
+// bb_internal.h -- declarations shared by the host API and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bbk {
+
+// Arguments of one bandwidth-reduction stage (see bb_kernels.hip).
+struct StageArgs {
+    void* W;            // working band base (element type = storage type)
+    int64_t S;          // ld_w - 1
+    int64_t uo;         // offset of the diagonal inside a band column
+    int n, b, tw, c, H; // order, bandwidth entering the stage, tilewidth, bandwidth left, half-step lag
+    int nsweeps;        // n - c - 1 (sweeps that exist in this stage)
+    int* progress;      // [nsweeps] half-step counters (zeroed before launch)
+    int* claim;         // [1] next sweep to hand out (zeroed before launch)
+    int* abort_flag;    // [1] watchdog abort word (zeroed before launch)
+    int* err_word;      // host-mapped error word
+    unsigned spin_limit;
+};
+
+hipError_t launch_pack(int dtype, const void* band, int64_t ldband, int64_t n, int64_t b_in, int64_t b, void* W,
+                       int64_t ldw, int64_t uo, float scale, hipStream_t st);
+hipError_t launch_extract(int dtype, const void* W, int64_t n, int64_t ldw, int64_t uo, double inv_scale, double* d,
+                          double* e, hipStream_t st);
+hipError_t launch_fill(int* p, int64_t count, int value, hipStream_t st);
+hipError_t launch_stage(int dtype, const StageArgs& a, int twm, int nt, int grid, hipStream_t st);
+
+}  // namespace bbk

@@ -1,0 +1,90 @@
+// bb_plan.cpp -- see bb_plan.h.
+#include "bb_plan.h"
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+namespace bbp {
+
+int min_lag(int c) { return c >= 3 ? 2 : (c == 2 ? 3 : 4); }
+
+Plan make_plan(int64_t b, int tw) {
+    Plan p;
+    while (b > 1) {
+        int t = (int)std::min<int64_t>(tw, b - 1);
+        int c = (int)(b - t);
+        p.stages.push_back(Stage{(int)b, t, c, min_lag(c)});
+        b = c;
+    }
+    return p;
+}
+
+int default_tw(int dtype) { return dtype == 0 ? 16 : 32; }
+
+int default_threads(int rows) {
+    int nt = 64;
+    while (nt < rows && nt < 512) nt *= 2;
+    return nt;
+}
+
+int kernel_twm(int tw) { return tw <= 8 ? 8 : tw <= 16 ? 16 : 32; }
+
+// Window of one step (rows k..p+m of columns p..p+m, and rows p..p+m of columns
+// p..L) holds (m+1)(L-k+1) elements; it is read and written once.
+double model_bytes(int64_t n, int64_t b, int elem, int tw) {
+    double elems = 0.0;
+    for (const Stage& s : make_plan(b, tw).stages) {
+        const int64_t bs = s.b, t = s.tw, c = s.c;
+        for (int64_t r = 0; r + c + 1 <= n - 1; ++r) {
+            // step 0
+            int64_t k = r, p = r + c, m = std::min(r + bs, n - 1) - p;
+            int64_t L = std::min(p + m + bs, n - 1);
+            elems += (double)(m + 1) * (double)(L - k + 1);
+            // steps j >= 1 with p_j = r + c + j*bs; interior ones (m = t, L = p+t+bs) in closed form
+            int64_t last_int = n - 1 - t - bs;  // p <= last_int  <=>  interior
+            int64_t j_int = (last_int >= r + c + bs) ? (last_int - r - c) / bs : 0;
+            elems += (double)j_int * (double)(t + 1) * (double)(2 * bs + t + 1);
+            for (int64_t j = j_int + 1;; ++j) {
+                p = r + c + j * bs;
+                k = p - bs;
+                m = std::min(t, n - 1 - p);
+                if (m < 1) break;
+                L = std::min(p + m + bs, n - 1);
+                elems += (double)(m + 1) * (double)(L - k + 1);
+            }
+        }
+    }
+    return 2.0 * elems * (double)elem;
+}
+
+namespace {
+std::mutex mu;
+std::map<std::tuple<int, int64_t, int>, Tuned> cache;
+int bucket(int64_t n) {
+    int l = 0;
+    while ((int64_t(1) << (l + 1)) <= n) ++l;
+    return l;
+}
+}  // namespace
+
+bool autotune_lookup(int64_t n, int64_t b, int dtype, Tuned* out) {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(std::make_tuple(bucket(n), b, dtype));
+    if (it == cache.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+void autotune_store(int64_t n, int64_t b, int dtype, const Tuned& t) {
+    std::lock_guard<std::mutex> lk(mu);
+    cache[std::make_tuple(bucket(n), b, dtype)] = t;
+}
+
+void autotune_clear() {
+    std::lock_guard<std::mutex> lk(mu);
+    cache.clear();
+}
+
+}  // namespace bbp

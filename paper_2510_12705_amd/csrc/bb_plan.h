@@ -1,0 +1,45 @@
+// bb_plan.h -- host-only planning: stages of the successive band reduction,
+// the half-step dependency lag, the algorithmic-bytes model and the autotune
+// cache.
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+namespace bbp {
+
+constexpr int kMaxTW = 32;
+
+struct Stage {
+    int b;    // bandwidth entering the stage
+    int tw;   // inner tilewidth of the stage, min(TW, b - 1)
+    int c;    // bandwidth left, b - tw
+    int lag;  // half-step lag between consecutive sweeps
+};
+
+struct Plan {
+    std::vector<Stage> stages;
+};
+
+// Stages of Algorithm 1's outer loop: reduce by TW until the band is bidiagonal.
+Plan make_plan(int64_t b, int tw);
+// Smallest half-step lag H for which concurrently running tasks of consecutive
+// sweeps are disjoint (see bb_kernels.hip): 2 for c >= 3, 3 for c = 2, 4 for c = 1.
+int min_lag(int c);
+
+int default_tw(int dtype);
+int default_threads(int rows);
+int kernel_twm(int tw);
+
+// Read + write bytes of the L-shaped window of every step, summed.
+double model_bytes(int64_t n, int64_t b, int elem, int tw);
+
+struct Tuned {
+    int tw, nt, wgs_per_cu;
+};
+bool autotune_lookup(int64_t n, int64_t b, int dtype, Tuned* out);
+void autotune_store(int64_t n, int64_t b, int dtype, const Tuned& t);
+void autotune_clear();
+
+}  // namespace bbp

@@ -1,0 +1,235 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+FP64 storage: the GPU kernels perform the oracle's arithmetic operation for
+operation (same sequential dot order, no fused multiply-add, the same LAPACK
+reflector formulas with correctly rounded division and square root), and
+concurrently running tasks touch disjoint data, so d and e must equal the
+oracle's BITWISE.  That meets the FP64 bar for (|d|, |e|) (1e-12 ||A||_F in
+2-norm) with zero difference, and sigma (computed from both by the same
+routine) trivially within 20 n eps64 sigma_max; both are still computed and
+asserted so a failure reports magnitudes.
+FP32 storage: max |sigma error| <= 50 n eps32 sigma_max against the FP64 oracle
+of the FP32-rounded input.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_2510_12705_amd import inputs  # noqa: E402
+from tests.pins import band_to_dense, dense_to_band  # noqa: E402
+
+EPS64 = np.finfo(np.float64).eps
+EPS32 = np.finfo(np.float32).eps
+
+
+@pytest.fixture(scope="module")
+def bb():
+    from paper_2510_12705_amd import bb as _bb
+    yield _bb
+    _bb.reset_params()
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_reduce(bb, band, n, b, dtype=torch.float64, **params):
+    bb.reset_params()
+    if params:
+        bb.set_params(**params)
+    t = torch.from_numpy(np.ascontiguousarray(band)).to("cuda:0").to(dtype)
+    d, e = bb.bb_reduce(t, n, b)
+    st = bb.stream_status()
+    assert st == 0, bb.bb_error_string(st)
+    return d.cpu().numpy(), e.cpu().numpy()
+
+
+def check_fp64(band, n, b, tw, d, e):
+    do, eo = oracle.reduce(band, n, b, tw)
+    normA = np.sqrt(np.sum(band * band))
+    de = np.sqrt(np.sum((np.abs(d) - np.abs(do)) ** 2) + np.sum((np.abs(e) - np.abs(eo)) ** 2))
+    s_g = oracle.singular_values(d, e)
+    s_o = oracle.singular_values(do, eo)
+    serr = np.max(np.abs(s_g - s_o)) if n else 0.0
+    first = np.flatnonzero((d != do)).tolist()[:3] + ["e"] + np.flatnonzero((e != eo)).tolist()[:3]
+    assert de <= 1e-12 * normA, ("|d|,|e| 2-norm difference", de, normA, first)
+    assert serr <= 20 * n * EPS64 * max(s_o[0], 1e-300), ("sigma", serr, s_o[0])
+    assert np.array_equal(d, do) and np.array_equal(e, eo), ("not bitwise equal", first)
+    return serr, de
+
+
+def test_c1_fp64_parity(bb):
+    n, b, tw = 512, 32, 16
+    _say("case n=512 b=32 fp64")
+    band = inputs.band_normal(n, b, seed=1)
+    d, e = gpu_reduce(bb, band, n, b, tw=tw)
+    check_fp64(band, n, b, tw, d, e)
+    A = band_to_dense(band, n, b)
+    assert d[0] == A[0, 0]
+
+
+RAGGED = [(300, 17, 4), (1000, 40, 16), (777, 64, 16), (1500, 100, 32), (129, 128, 16), (96, 200, 8),
+          (2049, 33, 16), (640, 9, 8), (513, 2, 1), (700, 3, 2), (333, 64, 1)]
+
+
+@pytest.mark.parametrize("n,b,tw", RAGGED)
+def test_ragged_fp64_parity(bb, n, b, tw):
+    _say("case n=%d b=%d tw=%d fp64" % (n, b, tw))
+    band = inputs.band_normal(n, b, seed=n + b)
+    d, e = gpu_reduce(bb, band, n, b, tw=tw)
+    check_fp64(band, n, b, tw, d, e)
+
+
+@pytest.mark.parametrize("nt", [64, 128, 256, 512])
+def test_thread_counts_are_bitwise_identical(bb, nt):
+    """Every thread count computes the same per-row/per-column arithmetic."""
+    n, b, tw = 700, 48, 16
+    band = inputs.band_normal(n, b, seed=3)
+    ref = gpu_reduce(bb, band, n, b, tw=tw, threads_per_window=256)
+    d, e = gpu_reduce(bb, band, n, b, tw=tw, threads_per_window=nt)
+    assert np.array_equal(d, ref[0]) and np.array_equal(e, ref[1])
+
+
+@pytest.mark.parametrize("spc", [1, 2, 16])
+def test_schedule_independence_bitwise(bb, spc):
+    """Race detector: concurrently running tasks are disjoint, so the grid size
+    (how many sweeps are in flight) must not change a single bit."""
+    n, b, tw = 3000, 64, 16
+    band = inputs.band_normal(n, b, seed=4)
+    ref = gpu_reduce(bb, band, n, b, tw=tw, sweeps_per_cu=8)
+    again = gpu_reduce(bb, band, n, b, tw=tw, sweeps_per_cu=8)
+    assert np.array_equal(again[0], ref[0]) and np.array_equal(again[1], ref[1])
+    d, e = gpu_reduce(bb, band, n, b, tw=tw, sweeps_per_cu=spc)
+    assert np.array_equal(d, ref[0]) and np.array_equal(e, ref[1])
+
+
+def test_larger_lag_is_bitwise_identical(bb):
+    n, b, tw = 1200, 40, 8
+    band = inputs.band_normal(n, b, seed=5)
+    ref = gpu_reduce(bb, band, n, b, tw=tw)
+    d, e = gpu_reduce(bb, band, n, b, tw=tw, lag=6)
+    assert np.array_equal(d, ref[0]) and np.array_equal(e, ref[1])
+
+
+def test_edge_cases(bb):
+    _say("case edge sizes")
+    # n = 1
+    d, e = gpu_reduce(bb, np.array([[0.0, 0.0, 2.5]]), 1, 2)
+    assert d.tolist() == [2.5]
+    # n = 2, b = 1
+    d, e = gpu_reduce(bb, np.array([[0.0, 1.0], [2.0, 3.0]]), 2, 1)
+    assert d.tolist() == [1.0, 3.0] and e.tolist() == [2.0]
+    # b = 0
+    d, e = gpu_reduce(bb, np.arange(1.0, 8.0).reshape(7, 1), 7, 0)
+    assert d.tolist() == [1, 2, 3, 4, 5, 6, 7] and e.tolist() == [0] * 6
+    # b >= n clamps
+    n = 20
+    band = inputs.band_normal(n, 30, seed=6)
+    d, e = gpu_reduce(bb, band, n, 30, tw=8)
+    s = oracle.singular_values(d, e)
+    assert np.max(np.abs(s - np.linalg.svd(band_to_dense(band, n, 30), compute_uv=False))) <= 1e-13 * s[0]
+    # ldband > b + 1 (padded input)
+    n, b = 300, 20
+    band = inputs.band_normal(n, b, seed=7)
+    padded = np.zeros((n, b + 5))
+    padded[:, : b + 1] = band
+    d1, e1 = gpu_reduce(bb, band, n, b, tw=8)
+    bb.set_params(tw=8)
+    t = torch.from_numpy(padded).cuda()
+    d2, e2 = bb.bb_reduce(t, n, b)
+    assert np.array_equal(d2.cpu().numpy(), d1) and np.array_equal(e2.cpu().numpy(), e1)
+
+
+@pytest.mark.parametrize("n,b,tw", [(200, 8, 3), (500, 33, 16)])
+def test_bidiagonal_input_unchanged(bb, n, b, tw):
+    rng = np.random.default_rng(11)
+    A = np.diag(rng.standard_normal(n)) + np.diag(rng.standard_normal(n - 1), 1)
+    band = dense_to_band(A, b)
+    d, e = gpu_reduce(bb, band, n, b, tw=tw)
+    assert np.array_equal(d, np.diag(A)) and np.array_equal(e, np.diag(A, 1))
+
+
+def test_tiny_scale_takes_rescaling_branch(bb):
+    """A band scaled by 2^-1000 drives every reflector through the |beta| < safmin
+    rescaling branch (and produces subnormal intermediates); the GPU must still
+    reproduce the oracle bitwise."""
+    n, b, tw = 400, 24, 16
+    band = inputs.band_normal(n, b, seed=8)
+    band[:, b] += 3.0 * np.sqrt(b + 1)
+    band *= 2.0 ** -1000
+    d, e = gpu_reduce(bb, band, n, b, tw=tw)
+    assert np.isfinite(d).all() and np.isfinite(e).all()
+    do, eo = oracle.reduce(band, n, b, tw)
+    assert np.array_equal(d, do) and np.array_equal(e, eo)
+
+
+def test_c2_fp64_parity(bb):
+    n, b, tw = 8192, 64, 16
+    _say("case n=8192 b=64 fp64 (oracle ~15 s)")
+    band = inputs.workload("n8192_b64")
+    d, e = gpu_reduce(bb, band, n, b, tw=tw)
+    serr, de = check_fp64(band, n, b, tw, d, e)
+    _say("  sigma err %.3e  |d,e| err %.3e" % (serr, de))
+
+
+def test_c2_graded_fp64_parity(bb):
+    n, b, tw = 8192, 64, 16
+    _say("case n=8192 b=64 graded fp64")
+    band = inputs.workload("n8192_b64_graded")
+    d, e = gpu_reduce(bb, band, n, b, tw=tw)
+    check_fp64(band, n, b, tw, d, e)
+
+
+@pytest.mark.parametrize("n,b,tw", [(512, 32, 32), (1000, 40, 16), (2000, 64, 32)])
+def test_fp32_storage_sigma_error(bb, n, b, tw):
+    _say("case n=%d b=%d fp32" % (n, b))
+    band = inputs.band_normal(n, b, seed=n)
+    band32 = band.astype(np.float32).astype(np.float64)
+    d, e = gpu_reduce(bb, band32, n, b, dtype=torch.float32, tw=tw)
+    do, eo = oracle.reduce(band32, n, b, tw)
+    s_g = oracle.singular_values(d, e)
+    s_o = oracle.singular_values(do, eo)
+    err = np.max(np.abs(s_g - s_o))
+    _say("  fp32 sigma err %.3e = %.3f n eps32 sigma_max" % (err, err / (n * EPS32 * s_o[0])))
+    assert err <= 50 * n * EPS32 * s_o[0]
+
+
+def _ata_frob2(band, n, b):
+    """||A^T A||_F^2 = sum sigma^4, from the band (A(i,j) = band[j, b+i-j])."""
+    # column j of A restricted to rows j-b..j is band[j, :]; (A^T A)_{j,j+o} = sum_i A_ij A_i,j+o
+    tot = 0.0
+    for o in range(0, b + 1):
+        # rows i with j-b <= i <= j and j+o-b <= i <= j+o  ->  i in [j+o-b, j]
+        x = band[: n - o, o:]              # A(i, j) for offsets b+i-j >= o
+        y = band[o:, : b + 1 - o]          # A(i, j+o) for the same rows
+        s = np.sum(x * y, axis=1)
+        tot += (1.0 if o == 0 else 2.0) * np.sum(s * s)
+    return tot
+
+
+def test_c3_fp64_properties_at_full_size(bb):
+    """n = 32768, b = 128 in the benchmark's launch configuration: properties that hold at
+    any size (the oracle needs minutes here): Frobenius norm, sum sigma^4, d0 exact,
+    |e0| = ||A[0, 1:]||, and bitwise determinism."""
+    n, b = 32768, 128
+    _say("case n=32768 b=128 fp64 properties")
+    band = inputs.workload("n32768_b128")
+    d, e = gpu_reduce(bb, band, n, b)
+    d2, e2 = gpu_reduce(bb, band, n, b)
+    assert np.array_equal(d, d2) and np.array_equal(e, e2)
+    assert np.isfinite(d).all() and np.isfinite(e).all()
+    A2 = np.sum(band * band)
+    assert abs(np.sum(d * d) + np.sum(e * e) - A2) <= 20 * n * EPS64 * A2
+    B4 = np.sum((d * d + np.concatenate([[0.0], e * e])) ** 2) + 2.0 * np.sum((d[:-1] * e) ** 2)
+    A4 = _ata_frob2(band, n, b)
+    assert abs(B4 - A4) <= 1e-11 * A4
+    assert d[0] == band[0, b]
+    row0 = np.array([band[j, b - j] for j in range(1, b + 1)])
+    assert abs(abs(e[0]) - np.linalg.norm(row0)) <= 8 * EPS64 * np.linalg.norm(row0)
