@@ -110,8 +110,10 @@ Workspace workspace_layout(int64_t n, int64_t b, int dtype, int tw) {
     w.nstages = (int)plan.stages.size();
     w.max_sweeps = std::max<int64_t>(n, 1);
     w.band_bytes = align_up((size_t)(n * w.ldw) * elem_size(dtype), 256);
-    // per stage: progress[max_sweeps], then claim + abort words
-    w.counter_bytes = align_up(sizeof(int) * (size_t)(w.nstages * w.max_sweeps + 2 * w.nstages + 2), 256);
+    // per stage: progress[max_sweeps]; then claim + abort words per stage; then the
+    // FP16 scale words (amax, exps[nstages + 1])
+    w.counter_bytes =
+        align_up(sizeof(int) * (size_t)(w.nstages * w.max_sweeps + 2 * w.nstages + 2 + w.nstages + 2), 256);
     w.total = w.band_bytes + w.counter_bytes;
     return w;
 }
@@ -149,7 +151,9 @@ int bb_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, int64_t 
     if (hipMallocAsync(&base, ws.total, st) != hipSuccess) return BB_ERR_NOMEM;
     char* W = (char*)base;
     int* counters = (int*)((char*)base + ws.band_bytes);
-    const int64_t ncounters = ws.nstages * ws.max_sweeps + 2 * ws.nstages + 2;
+    const int64_t ncounters = ws.nstages * ws.max_sweeps + 2 * ws.nstages + 2 + ws.nstages + 2;
+    unsigned* f16_amax = (unsigned*)(counters + ws.nstages * ws.max_sweeps + 2 * ws.nstages + 2);
+    int* f16_exps = (int*)(f16_amax + 1);  // nstages + 1 exponents, zero-initialised
 
     float scale = 1.0f;
     double inv_scale = 1.0;
@@ -173,6 +177,9 @@ int bb_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, int64_t 
         a.err_word = ds->err_dev;
         a.spin_limit = spin_limit();
         if (a.nsweeps == 0) continue;
+        if (dtype == BB_F16)
+            rc = check_hip(bbk::launch_f16_rescale(W, n * ws.ldw, f16_amax, f16_exps, s, st));
+        if (rc) break;
         const int twm = bbp::kernel_twm(sg.tw);
         const int grid = (int)std::min<int64_t>(a.nsweeps, (int64_t)ds->cus * L.wgs_per_cu);
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -190,7 +197,14 @@ int bb_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, int64_t 
             g_timing.events.emplace_back(e0, e1);
         }
     }
-    if (!rc) rc = check_hip(bbk::launch_extract(dtype, W, n, ws.ldw, ws.uo, inv_scale, d, e, st));
+    if (!rc) {
+        if (dtype == BB_F16) {
+            // every stage has n - c - 1 >= 1 sweeps (c <= b - 1 <= n - 2), so each one rescaled
+            rc = check_hip(bbk::launch_extract_f16(W, n, ws.ldw, ws.uo, f16_exps, ws.nstages, d, e, st));
+        } else {
+            rc = check_hip(bbk::launch_extract(dtype, W, n, ws.ldw, ws.uo, inv_scale, d, e, st));
+        }
+    }
     hipError_t fe = hipFreeAsync(base, st);
     if (!rc && fe != hipSuccess) rc = BB_ERR_HIP;
     return rc;

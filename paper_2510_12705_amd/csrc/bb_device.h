@@ -16,6 +16,11 @@ constexpr int kDone = 0x7fffffff;  // progress value of a sweep that, and all sw
 // ---------------------------------------------------------------------------
 // lane broadcast (full wave active)
 // ---------------------------------------------------------------------------
+// x on lanes 0..m, +0 on lanes above m
+__device__ __forceinline__ double mask_above(double x, int m) {
+    return (int)(threadIdx.x & 63) <= m ? x : 0.0;
+}
+
 __device__ __forceinline__ double readlane_f64(double x, int lane) {
     int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
     int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
@@ -83,14 +88,36 @@ __device__ __forceinline__ double nrm2_finish(bool notbig, double asml, double a
     return scl * sqrt(sumsq);
 }
 
-template <int TWM>
-__device__ __forceinline__ double nrm2_uniform(const double (&x)[TWM + 1], int m) {
+// General xNRM2 over lanes 1..m of xm, each value first multiplied knt times by
+// 2^970 (the xLARFG rescaling).  Rarely taken, so kept out of line as a loop.
+__device__ __noinline__ double nrm2_lanes_general(double xm, int m, int knt) {
+    constexpr double rsafmn = 2.220446049250313e-16 / 2.2250738585072014e-308;  // 1 / safmin = 2^970
     bool notbig = true;
     double asml = 0.0, amed = 0.0, abig = 0.0;
-#pragma unroll
-    for (int t = 1; t <= TWM; ++t)
-        if (t <= m) nrm2_uniform_step(fabs(x[t]), notbig, asml, amed, abig);
+    for (int t = 1; t <= m; ++t) {
+        double xt = readlane_f64(xm, t);
+        for (int i = 0; i < knt; ++i) xt = xt * rsafmn;
+        nrm2_uniform_step(fabs(xt), notbig, asml, amed, abig);
+    }
     return nrm2_finish(notbig, asml, amed, abig);
+}
+
+// xNRM2 of x[1..m] (x[t] == 0 for t > m).  When every nonzero |x_t| lies in
+// [tsml, tbig] it reduces to sqrt of the plain left-to-right sum of squares
+// (zeros add exactly +0); otherwise the general algorithm runs on the lanes.
+template <int TWM>
+__device__ __forceinline__ double nrm2_uniform(const double (&x)[TWM + 1], double xm, int m) {
+    constexpr double tsml = 0x1p-511, tbig = 0x1p486;
+    bool mid = true;
+    double amed = 0.0;
+#pragma unroll
+    for (int t = 1; t <= TWM; ++t) {
+        const double ax = fabs(x[t]);
+        mid = mid & ((ax == 0.0) | ((ax >= tsml) & (ax <= tbig)));
+        amed = amed + ax * ax;
+    }
+    if (mid) return sqrt(amed);
+    return nrm2_lanes_general(xm, m, 0);
 }
 
 __device__ __forceinline__ double lapy2(double a, double b) {
@@ -107,10 +134,11 @@ template <int TWM>
 __device__ __forceinline__ void house_uniform(double x_lane, int m, double (&v)[TWM + 1], double& tau,
                                               double& beta) {
     double x[TWM + 1];
+    const double xm = mask_above(x_lane, m);
 #pragma unroll
-    for (int t = 0; t <= TWM; ++t) x[t] = t <= m ? readlane_f64(x_lane, t) : 0.0;
+    for (int t = 0; t <= TWM; ++t) x[t] = readlane_f64(xm, t);
     double alpha = x[0];
-    double xn = nrm2_uniform<TWM>(x, m);
+    double xn = nrm2_uniform<TWM>(x, xm, m);
     v[0] = 1.0;
     if (xn == 0.0) {
 #pragma unroll
@@ -124,21 +152,23 @@ __device__ __forceinline__ void house_uniform(double x_lane, int m, double (&v)[
     constexpr double safmin = 2.2250738585072014e-308 / 2.220446049250313e-16;  // DBL_MIN / DBL_EPSILON
     int knt = 0;
     if (fabs(bt) < safmin) {
-        const double rsafmn = 1.0 / safmin;
+        constexpr double rsafmn = 1.0 / safmin;
         do {
             ++knt;
-#pragma unroll
-            for (int t = 1; t <= TWM; ++t) x[t] = x[t] * rsafmn;
             bt = bt * rsafmn;
             alpha = alpha * rsafmn;
         } while (fabs(bt) < safmin && knt < 20);
-        xn = nrm2_uniform<TWM>(x, m);
+        for (int i = 0; i < knt; ++i) {
+#pragma unroll
+            for (int t = 1; t <= TWM; ++t) x[t] = x[t] * rsafmn;  // exact power-of-two scaling
+        }
+        xn = nrm2_lanes_general(xm, m, knt);
         h = lapy2(alpha, xn);
         bt = alpha >= 0.0 ? -h : h;
     }
     const double scal = 1.0 / (alpha - bt);
 #pragma unroll
-    for (int t = 1; t <= TWM; ++t) v[t] = t <= m ? x[t] * scal : 0.0;
+    for (int t = 1; t <= TWM; ++t) v[t] = x[t] * scal;  // x[t] == 0 for t > m
     tau = (bt - alpha) / bt;
     for (int i = 0; i < knt; ++i) bt = bt * safmin;
     beta = bt;
@@ -195,11 +225,17 @@ __device__ __forceinline__ bool wait_ge(const int* flag, int target, const SyncC
     return *lds_ok != 0;
 }
 
-// All threads call this after their last store of a task.
+// All threads call this after their last store of a task.  Every wave first
+// drains its own outstanding memory operations (so its stores have reached the
+// L2 of this XCD), the block synchronises, and thread 0 alone then performs the
+// agent-scope release (one L2 write-back for the whole block) and the flag store.
 __device__ __forceinline__ void publish(int* flag, int value) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(flag, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(flag, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 }  // namespace bbk

@@ -83,6 +83,51 @@ __global__ void bb_extract(const T* __restrict__ W, int64_t n, int64_t ldw, int6
     }
 }
 
+// FP16 storage: per-stage power-of-two scale.  amax receives the bit pattern of
+// max |W| (non-negative floats order like their bit patterns); the rescale
+// kernel then multiplies every entry by 2^(e_new - e_old), where e_new puts
+// max |W| in [2^kF16Top, 2^(kF16Top+1)).  Multiplying by a power of two is exact
+// unless a value leaves the FP16 range.  exps[s] is the exponent in force
+// before stage s's rescale; exps[s+1] after it.
+constexpr int kF16Top = 11;
+
+__global__ void bb_absmax_f16(const _Float16* __restrict__ W, int64_t count, unsigned* __restrict__ amax) {
+    float m = 0.f;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, fabsf(static_cast<float>(W[i])));
+    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(amax, __float_as_uint(m));
+}
+
+__device__ __forceinline__ int f16_target_exp(unsigned amax_bits, int e_old) {
+    const float m = __uint_as_float(amax_bits);
+    if (!(m > 0.f) || !isfinite(m)) return e_old;
+    return e_old + (kF16Top - ilogbf(m));
+}
+
+__global__ void bb_rescale_f16(_Float16* __restrict__ W, int64_t count, const unsigned* __restrict__ amax,
+                               int* __restrict__ exps, int s) {
+    const int e_old = exps[s];
+    const int e_new = f16_target_exp(*amax, e_old);
+    if (blockIdx.x == 0 && threadIdx.x == 0) exps[s + 1] = e_new;
+    const int de = e_new - e_old;
+    if (de == 0) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        W[i] = static_cast<_Float16>(ldexpf(static_cast<float>(W[i]), de));
+}
+
+__global__ void bb_extract_f16(const _Float16* __restrict__ W, int64_t n, int64_t ldw, int64_t uo,
+                               const int* __restrict__ exps, int nexp, double* __restrict__ d,
+                               double* __restrict__ e) {
+    const _Float16* A = W + uo;
+    const int64_t S = ldw - 1;
+    const int ex = exps[nexp];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        d[i] = ldexp(static_cast<double>(A[i + i * S]), -ex);
+        if (i + 1 < n) e[i] = ldexp(static_cast<double>(A[i + (i + 1) * S]), -ex);
+    }
+}
+
 __global__ void bb_fill_i32(int* __restrict__ p, int64_t count, int value) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = value;
@@ -100,31 +145,79 @@ __global__ void bb_fill_i32(int* __restrict__ p, int64_t count, int value) {
 template <typename C, int TWM>
 __device__ __forceinline__ void apply_segment(C (&av)[TWM + 1], const C (&vs)[TWM + 1], C tau, int m) {
     if constexpr (std::is_same<C, double>::value) {
+        // entries t > m are +0 in av and vs: they add exactly 0 and stay 0
         double w = 0.0;
 #pragma unroll
-        for (int t = 0; t <= TWM; ++t)
-            if (t <= m) w = w + av[t] * vs[t];
+        for (int t = 0; t <= TWM; ++t) w = w + av[t] * vs[t];
         const double tw = tau * w;
 #pragma unroll
-        for (int t = 0; t <= TWM; ++t)
-            if (t <= m) av[t] = av[t] - tw * vs[t];
+        for (int t = 0; t <= TWM; ++t) av[t] = av[t] - tw * vs[t];
     } else {
         float s = 0.f, comp = 0.f;
 #pragma unroll
         for (int t = 0; t <= TWM; ++t) {
-            if (t <= m) {
-                const float pr = av[t] * vs[t];
-                const float ep = fmaf(av[t], vs[t], -pr);
-                float es;
-                two_sum(s, pr, s, es);
-                comp = comp + (es + ep);
-            }
+            const float pr = av[t] * vs[t];
+            const float ep = fmaf(av[t], vs[t], -pr);
+            float es;
+            two_sum(s, pr, s, es);
+            comp = comp + (es + ep);
         }
         const float tw = tau * (s + comp);
 #pragma unroll
-        for (int t = 0; t <= TWM; ++t)
-            if (t <= m) av[t] = fmaf(-tw, vs[t], av[t]);
+        for (int t = 0; t <= TWM; ++t) av[t] = fmaf(-tw, vs[t], av[t]);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Window segment movement.  Entry t of a segment lives at column / row offset
+// min(t, m) (always inside the window); entries t > m are masked to 0 on load
+// and re-store the value of entry m on store, so no per-element branch is needed.
+// ---------------------------------------------------------------------------
+// `base` points at A(k, p) of the current step; in-window offsets fit in 32 bits.
+template <typename T, typename C, int TWM>
+__device__ __forceinline__ void load_row(C (&av)[TWM + 1], const T* __restrict__ base, int S, int di, int m) {
+    const T* row = base + di;  // A(k + di, p + t) = row[t * S]
+#pragma unroll
+    for (int t = 0; t <= TWM; ++t) {
+        const C v = to_c(row[min(t, m) * S]);
+        av[t] = t <= m ? v : C(0);
+    }
+}
+
+template <typename T, typename C, int TWM>
+__device__ __forceinline__ void store_row(const C (&av)[TWM + 1], T* __restrict__ base, int S, int di, int m) {
+    T* row = base + di;
+#pragma unroll
+    for (int t = 0; t <= TWM; ++t) row[min(t, m) * S] = static_cast<T>(av[min(t, m)]);
+}
+
+// column q = p + 1 + ci of rows p..p+m; columns p+1..p+m come from the LDS corner
+// `base` points at A(p, p); column q = p + 1 + ci starts at base + (1 + ci) * S.
+template <typename T, typename C, int TWM>
+__device__ __forceinline__ void load_col(C (&av)[TWM + 1], const T* __restrict__ base, int S, const C* corner, int ci,
+                                         int m) {
+    constexpr int LDC = TWM + 1;
+    if (ci < m) {
+#pragma unroll
+        for (int t = 0; t <= TWM; ++t) {
+            const C v = corner[min(t, m) * LDC + ci + 1];
+            av[t] = t <= m ? v : C(0);
+        }
+    } else {
+        const T* col = base + (1 + ci) * S;  // A(p + t, q) = col[t]
+#pragma unroll
+        for (int t = 0; t <= TWM; ++t) {
+            const C v = to_c(col[min(t, m)]);
+            av[t] = t <= m ? v : C(0);
+        }
+    }
+}
+
+template <typename T, typename C, int TWM>
+__device__ __forceinline__ void store_col(const C (&av)[TWM + 1], T* __restrict__ base, int S, int ci, int m) {
+    T* col = base + (1 + ci) * S;
+#pragma unroll
+    for (int t = 0; t <= TWM; ++t) col[min(t, m)] = static_cast<T>(av[min(t, m)]);
 }
 
 // ---------------------------------------------------------------------------
@@ -141,6 +234,7 @@ __global__ __launch_bounds__(NT) void bb_stage(StageArgs a) {
     const int lane = tid & (kWave - 1);
     T* __restrict__ A = reinterpret_cast<T*>(a.W) + a.uo;
     const int64_t S = a.S;
+    const int S32 = (int)a.S;
     const int n = a.n, b = a.b, tw = a.tw, c = a.c, H = a.H;
     const SyncCtx sc{a.abort_flag, a.err_word, a.spin_limit};
 
@@ -170,18 +264,18 @@ __global__ __launch_bounds__(NT) void bb_stage(StageArgs a) {
             }
 
             // ------------------------- right (row) task -------------------------
-            // reflector from A[k, p..p+m]; applied to rows k+1..p+m of columns p..p+m
+            // reflector from A[k, p..p+m]; applied to rows k+1..p+m of columns p..p+m.
+            // Loads are issued before the reflector is formed so their latency overlaps
+            // it; column indices are clamped to p+min(t, m) so every access stays in the
+            // window without per-element branches, and entries t > m are masked to 0.
             if (prev && !wait_ge(prev, 2 * j + H, sc, &s_word[1])) return;
             {
                 const int rows = p + m - k;
+                T* base = A + k + (int64_t)p * S;  // A(k, p)
+                const double xl = static_cast<double>(base[min(lane, m) * S32]);
                 int ri = tid;
                 C av[TWM + 1];
-                if (ri < rows) {
-                    const T* row = A + (k + 1 + ri) + (int64_t)p * S;
-#pragma unroll
-                    for (int t = 0; t <= TWM; ++t) av[t] = t <= m ? to_c(row[(int64_t)t * S]) : C(0);
-                }
-                const double xl = lane <= m ? static_cast<double>(A[k + (int64_t)(p + lane) * S]) : 0.0;
+                load_row<T, C, TWM>(av, base, S32, 1 + min(ri, rows - 1), m);
                 double vd[TWM + 1], taud, betad;
                 house_uniform<TWM>(xl, m, vd, taud, betad);
                 C vs[TWM + 1];
@@ -193,27 +287,17 @@ __global__ __launch_bounds__(NT) void bb_stage(StageArgs a) {
                     if (taud != 0.0) apply_segment<C, TWM>(av, vs, tau, m);
                     if (i >= p) {  // bottom (m+1) x (m+1) corner stays on chip for the left task
 #pragma unroll
-                        for (int t = 0; t <= TWM; ++t)
-                            if (t <= m) corner[(i - p) * LDC + t] = av[t];
+                        for (int t = 0; t <= TWM; ++t) corner[(i - p) * LDC + t] = av[t];
                     } else {
-                        T* row = A + i + (int64_t)p * S;
-#pragma unroll
-                        for (int t = 0; t <= TWM; ++t)
-                            if (t <= m) row[(int64_t)t * S] = static_cast<T>(av[t]);
+                        store_row<T, C, TWM>(av, base, S32, 1 + ri, m);
                     }
                     ri += NT;
-                    if (ri < rows) {
-                        const T* row = A + (k + 1 + ri) + (int64_t)p * S;
-#pragma unroll
-                        for (int t = 0; t <= TWM; ++t) av[t] = t <= m ? to_c(row[(int64_t)t * S]) : C(0);
-                    }
+                    if (ri < rows) load_row<T, C, TWM>(av, base, S32, 1 + ri, m);
                 }
                 // every wave has read row k: now overwrite it with (beta, 0, ..., 0)
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 __syncthreads();
-                if (tid <= m) A[k + (int64_t)(p + tid) * S] = static_cast<T>(tid == 0 ? betad : 0.0);
-                if (tid < kWave) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                if (tid == 0) __hip_atomic_store(mine, 2 * j + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (tid <= m) base[tid * S32] = static_cast<T>(tid == 0 ? betad : 0.0);
+                publish(mine, 2 * j + 1);
             }
 
             // ------------------------- left (column) task -------------------------
@@ -224,18 +308,10 @@ __global__ __launch_bounds__(NT) void bb_stage(StageArgs a) {
                 const int L = min(p + m + b, n - 1);
                 const int cols = L - p;  // columns p+1 .. L
                 int ci = tid;
+                T* base = A + p + (int64_t)p * S;  // A(p, p)
                 C av[TWM + 1];
-                if (ci < cols) {
-                    if (ci < m) {
-#pragma unroll
-                        for (int t = 0; t <= TWM; ++t) av[t] = t <= m ? corner[t * LDC + ci + 1] : C(0);
-                    } else {
-                        const T* col = A + p + (int64_t)(p + 1 + ci) * S;
-#pragma unroll
-                        for (int t = 0; t <= TWM; ++t) av[t] = t <= m ? to_c(col[t]) : C(0);
-                    }
-                }
-                const double xl = lane <= m ? static_cast<double>(corner[lane * LDC]) : 0.0;
+                load_col<T, C, TWM>(av, base, S32, corner, min(ci, cols - 1), m);
+                const double xl = static_cast<double>(corner[min(lane, m) * LDC]);
                 double vd[TWM + 1], taud, betad;
                 house_uniform<TWM>(xl, m, vd, taud, betad);
                 C vs[TWM + 1];
@@ -243,24 +319,12 @@ __global__ __launch_bounds__(NT) void bb_stage(StageArgs a) {
                 for (int t = 0; t <= TWM; ++t) vs[t] = static_cast<C>(vd[t]);
                 const C tau = static_cast<C>(taud);
                 while (ci < cols) {
-                    T* col = A + p + (int64_t)(p + 1 + ci) * S;  // A(p, q), q = p+1+ci
                     if (taud != 0.0) apply_segment<C, TWM>(av, vs, tau, m);
-#pragma unroll
-                    for (int t = 0; t <= TWM; ++t)
-                        if (t <= m) col[t] = static_cast<T>(av[t]);
+                    store_col<T, C, TWM>(av, base, S32, ci, m);
                     ci += NT;
-                    if (ci < cols) {
-                        if (ci < m) {
-#pragma unroll
-                            for (int t = 0; t <= TWM; ++t) av[t] = t <= m ? corner[t * LDC + ci + 1] : C(0);
-                        } else {
-                            const T* nc = A + p + (int64_t)(p + 1 + ci) * S;
-#pragma unroll
-                            for (int t = 0; t <= TWM; ++t) av[t] = t <= m ? to_c(nc[t]) : C(0);
-                        }
-                    }
+                    if (ci < cols) load_col<T, C, TWM>(av, base, S32, corner, ci, m);
                 }
-                if (tid <= m) A[p + tid + (int64_t)p * S] = static_cast<T>(tid == 0 ? betad : 0.0);
+                if (tid <= m) base[tid] = static_cast<T>(tid == 0 ? betad : 0.0);
                 publish(mine, 2 * j + 2);
             }
         }
@@ -310,6 +374,25 @@ hipError_t launch_extract(int dtype, const void* W, int64_t n, int64_t ldw, int6
         case 1: return launch_extract_t<float>(W, n, ldw, uo, inv_scale, d, e, st);
         default: return launch_extract_t<_Float16>(W, n, ldw, uo, inv_scale, d, e, st);
     }
+}
+
+hipError_t launch_f16_rescale(void* W, int64_t count, unsigned* amax, int* exps, int s, hipStream_t st) {
+    int grid = (int)std::min<int64_t>((count + 255) / 256, 2048);
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(bb_fill_i32, dim3(1), dim3(64), 0, st, reinterpret_cast<int*>(amax), (int64_t)1, 0);
+    hipLaunchKernelGGL(bb_absmax_f16, dim3(grid), dim3(256), 0, st, static_cast<const _Float16*>(W), count, amax);
+    hipLaunchKernelGGL(bb_rescale_f16, dim3(grid), dim3(256), 0, st, static_cast<_Float16*>(W), count,
+                       (const unsigned*)amax, exps, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_extract_f16(const void* W, int64_t n, int64_t ldw, int64_t uo, const int* exps, int nexp,
+                              double* d, double* e, hipStream_t st) {
+    int grid = (int)std::min<int64_t>((n + 255) / 256, 65536);
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(bb_extract_f16, dim3(grid), dim3(256), 0, st, static_cast<const _Float16*>(W), n, ldw, uo,
+                       exps, nexp, d, e);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill(int* p, int64_t count, int value, hipStream_t st) {
