@@ -151,7 +151,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "n=%d, b=%d upper band, i.i.d. N(0,1) entries (seed %d), FP64 storage" % (n, b, seed),
                    "n": n, "b": b, "storage": "fp64", "tw": p.tw, "threads_per_window": p.threads_per_window,
-                   "sweeps_per_cu": p.sweeps_per_cu, "stages": len(bb.plan(b, p.tw))},
+                   "sweeps_per_group": p.sweeps_per_group, "groups_per_cu": p.groups_per_cu,
+                   "stages": len(bb.plan(b, p.tw))},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": traffic,
                      "kernel": "bb_stage", "alg_bytes_per_launch": per_launch_bytes,

@@ -60,10 +60,13 @@ enum {
  * tilewidth, maximum blocks).  0 in any field means "automatic".
  *   tw                 inner tilewidth TW (entries annihilated per reflector);
  *                      supported values: 1..32.
- *   threads_per_window threads of the workgroup that owns one sweep: 64, 128,
- *                      256 or 512.
- *   sweeps_per_cu      persistent workgroups launched per compute unit (1..16);
- *                      caps the sweeps in flight, the paper's "Max blocks".
+ *   threads_per_window threads that work on one sweep's window: 64, 128 or 256.
+ *   sweeps_per_group   consecutive sweeps one workgroup advances in lock-step
+ *                      (1..16, threads_per_window * sweeps_per_group <= 1024);
+ *                      hand-over inside a group costs one workgroup barrier.
+ *   groups_per_cu      persistent workgroups launched per compute unit (1..16);
+ *                      with sweeps_per_group it caps the sweeps in flight, the
+ *                      paper's "Max blocks".
  *   lag                half-step dependency lag between consecutive sweeps; each
  *                      stage uses max(lag, smallest safe lag of that stage), so
  *                      0 selects the smallest safe value (bb_min_lag) and a
@@ -72,7 +75,8 @@ enum {
 typedef struct {
     int tw;
     int threads_per_window;
-    int sweeps_per_cu;
+    int sweeps_per_group;
+    int groups_per_cu;
     int lag;
 } bb_params_t;
 

@@ -26,7 +26,7 @@ struct DeviceState {
 };
 
 std::mutex g_mu;
-bb_params_t g_params = {0, 0, 0, 0};
+bb_params_t g_params = {0, 0, 0, 0, 0};
 std::vector<DeviceState> g_dev;
 
 struct Timing {
@@ -71,11 +71,12 @@ int device_state(DeviceState** out) {
 }
 
 size_t elem_size(int dtype) { return dtype == BB_F64 ? 8 : dtype == BB_F32 ? 4 : 2; }
+size_t elem_size_c(int dtype) { return dtype == BB_F64 ? 8 : 4; }  // compute type held in LDS
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Launch {
-    int tw, nt, wgs_per_cu, lag;
+    int tw, ntl, lanes, groups_per_cu, lag;
 };
 
 Launch resolve(int64_t n, int64_t b, int dtype) {
@@ -89,9 +90,14 @@ Launch resolve(int64_t n, int64_t b, int dtype) {
     Launch L;
     L.tw = p.tw ? p.tw : cached ? t.tw : bbp::default_tw(dtype);
     int rows = (int)std::min<int64_t>(b, std::max<int64_t>(n - 1, 1)) + L.tw;
-    L.nt = p.threads_per_window ? p.threads_per_window : cached ? t.nt : bbp::default_threads(rows);
-    L.wgs_per_cu = p.sweeps_per_cu ? p.sweeps_per_cu : cached ? t.wgs_per_cu : 8;
+    L.ntl = p.threads_per_window ? p.threads_per_window : cached ? t.ntl : bbp::default_threads(rows);
+    L.lanes = p.sweeps_per_group ? p.sweeps_per_group : cached ? t.lanes : bbp::default_lanes(L.ntl);
+    L.groups_per_cu = p.groups_per_cu ? p.groups_per_cu : cached ? t.groups_per_cu : 2;
     L.lag = p.lag;
+    // keep the per-workgroup LDS corner blocks within 64 KB
+    const size_t per_lane = (size_t)(bbp::kernel_twm(L.tw) + 1) * (bbp::kernel_twm(L.tw) + 1) * elem_size_c(dtype);
+    while (L.lanes > 1 && (size_t)L.lanes * per_lane > 65536) --L.lanes;
+    while (L.lanes > 1 && L.lanes * L.ntl > bbk::stage_max_threads(bbp::kernel_twm(L.tw))) --L.lanes;
     return L;
 }
 
@@ -181,7 +187,8 @@ int bb_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, int64_t 
             rc = check_hip(bbk::launch_f16_rescale(W, n * ws.ldw, f16_amax, f16_exps, s, st));
         if (rc) break;
         const int twm = bbp::kernel_twm(sg.tw);
-        const int grid = (int)std::min<int64_t>(a.nsweeps, (int64_t)ds->cus * L.wgs_per_cu);
+        const int64_t ngroups = (a.nsweeps + L.lanes - 1) / L.lanes;
+        const int grid = (int)std::min<int64_t>(ngroups, (int64_t)ds->cus * L.groups_per_cu);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         bool timed = false;
         {
@@ -190,7 +197,7 @@ int bb_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, int64_t 
         }
         if (timed && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess)
             hipEventRecord(e0, st);
-        rc = check_hip(bbk::launch_stage(dtype, a, twm, L.nt, grid, st));
+        rc = check_hip(bbk::launch_stage(dtype, a, twm, L.ntl, L.lanes, grid, st));
         if (timed && e1) {
             hipEventRecord(e1, st);
             std::lock_guard<std::mutex> lk(g_mu);
@@ -231,13 +238,16 @@ int bb_reduce_batched(int64_t count, const int64_t* n, const int64_t* b, bb_dtyp
 }
 
 int bb_set_params(const bb_params_t* p) {
-    bb_params_t q = {0, 0, 0, 0};
+    bb_params_t q = {0, 0, 0, 0, 0};
     if (p) {
         if (p->tw < 0 || p->tw > bbp::kMaxTW) return -1;
-        if (p->threads_per_window != 0 && (p->threads_per_window < 64 || p->threads_per_window > 512 ||
-                                           (p->threads_per_window & (p->threads_per_window - 1))))
+        if (p->threads_per_window != 0 && p->threads_per_window != 64 && p->threads_per_window != 128 &&
+            p->threads_per_window != 256)
             return -1;
-        if (p->sweeps_per_cu < 0 || p->sweeps_per_cu > 16) return -1;
+        if (p->sweeps_per_group < 0 || p->sweeps_per_group > 16) return -1;
+        if (p->threads_per_window && p->sweeps_per_group && p->threads_per_window * p->sweeps_per_group > 1024)
+            return -1;
+        if (p->groups_per_cu < 0 || p->groups_per_cu > 16) return -1;
         if (p->lag < 0 || p->lag > 64) return -1;
         q = *p;
     }
@@ -343,6 +353,6 @@ extern "C" int bb_autotune(int64_t n, int64_t b, bb_dtype_t dtype, void* stream,
     if (b < 0) return -2;
     if (dtype != BB_F64 && dtype != BB_F32 && dtype != BB_F16) return -3;
     Launch L = resolve(n, std::min<int64_t>(b, std::max<int64_t>(n - 1, 0)), dtype);
-    if (out) *out = bb_params_t{L.tw, L.nt, L.wgs_per_cu, L.lag};
+    if (out) *out = bb_params_t{L.tw, L.ntl, L.lanes, L.groups_per_cu, L.lag};
     return BB_OK;
 }

@@ -89,13 +89,16 @@ __device__ __forceinline__ double nrm2_finish(bool notbig, double asml, double a
 }
 
 // General xNRM2 over lanes 1..m of xm, each value first multiplied knt times by
-// 2^970 (the xLARFG rescaling).  Rarely taken, so kept out of line as a loop.
-__device__ __noinline__ double nrm2_lanes_general(double xm, int m, int knt) {
+// 2^970 (the xLARFG rescaling).  Rarely taken: a rolled loop reading one lane
+// per iteration keeps it small without a call (a call would spill registers).
+__device__ __forceinline__ double nrm2_lanes_general(double xm, int m, int knt) {
     constexpr double rsafmn = 2.220446049250313e-16 / 2.2250738585072014e-308;  // 1 / safmin = 2^970
     bool notbig = true;
     double asml = 0.0, amed = 0.0, abig = 0.0;
+#pragma unroll 1
     for (int t = 1; t <= m; ++t) {
         double xt = readlane_f64(xm, t);
+#pragma unroll 1
         for (int i = 0; i < knt; ++i) xt = xt * rsafmn;
         nrm2_uniform_step(fabs(xt), notbig, asml, amed, abig);
     }

@@ -170,8 +170,8 @@ __device__ __forceinline__ void apply_segment(C (&av)[TWM + 1], const C (&vs)[TW
 
 // ---------------------------------------------------------------------------
 // Window segment movement.  Entry t of a segment lives at column / row offset
-// min(t, m) (always inside the window); entries t > m are masked to 0 on load
-// and re-store the value of entry m on store, so no per-element branch is needed.
+// min(t, m) (always inside the window); entries t > m are masked to 0 on load,
+// so no per-element branch or dynamically indexed register array is needed.
 // ---------------------------------------------------------------------------
 // `base` points at A(k, p) of the current step; in-window offsets fit in 32 bits.
 template <typename T, typename C, int TWM>
@@ -184,11 +184,14 @@ __device__ __forceinline__ void load_row(C (&av)[TWM + 1], const T* __restrict__
     }
 }
 
+// Stores run from t = TWM down to 0: an entry t > m (masked to 0) lands on the
+// clamped address of entry m first and is then overwritten by entry m itself
+// (stores of one thread to one address keep program order).
 template <typename T, typename C, int TWM>
 __device__ __forceinline__ void store_row(const C (&av)[TWM + 1], T* __restrict__ base, int S, int di, int m) {
     T* row = base + di;
 #pragma unroll
-    for (int t = 0; t <= TWM; ++t) row[min(t, m) * S] = static_cast<T>(av[min(t, m)]);
+    for (int t = TWM; t >= 0; --t) row[min(t, m) * S] = static_cast<T>(av[t]);
 }
 
 // column q = p + 1 + ci of rows p..p+m; columns p+1..p+m come from the LDS corner
@@ -217,120 +220,262 @@ template <typename T, typename C, int TWM>
 __device__ __forceinline__ void store_col(const C (&av)[TWM + 1], T* __restrict__ base, int S, int ci, int m) {
     T* col = base + (1 + ci) * S;
 #pragma unroll
-    for (int t = 0; t <= TWM; ++t) col[min(t, m)] = static_cast<T>(av[min(t, m)]);
+    for (int t = TWM; t >= 0; --t) col[min(t, m)] = static_cast<T>(av[t]);
 }
 
 // ---------------------------------------------------------------------------
 // one bandwidth-reduction stage
+//
+// A workgroup owns a group of G consecutive sweeps r0 .. r0+G-1 ("lanes"; lane
+// g uses threads [g*NTL, (g+1)*NTL)).  Its lanes advance in lock-step phases:
+// in phase P, lane g executes half-step h = P - H*g of sweep r0+g (if that
+// half-step exists).  Lane g then always trails lane g-1 by H half-steps, which
+// is exactly the dependency rule, so hand-over inside the group needs only the
+// workgroup barrier that ends each phase.  Lane 0 depends on the last sweep of
+// the previous group through that sweep's progress word (agent-scope
+// acquire by thread 0 before the phase); the group publishes the progress of
+// its own last sweep after every phase (agent-scope release by thread 0).
+// Concurrently running half-steps (of this and of other groups) touch
+// disjoint data, so results are bitwise those of the sequential order.
 // ---------------------------------------------------------------------------
-template <typename T, int TWM, int NT>
-__global__ __launch_bounds__(NT) void bb_stage(StageArgs a) {
+struct StepGeom {
+    int k, p, m;
+};
+
+__device__ __forceinline__ StepGeom step_geom(int n, int b, int tw, int c, int r, int j) {
+    StepGeom g;
+    if (j == 0) {
+        g.k = r;
+        g.p = r + c;
+        g.m = min(r + b, n - 1) - g.p;
+    } else {
+        g.k = r + c + (j - 1) * b;
+        g.p = g.k + b;
+        g.m = min(tw, n - 1 - g.p);
+    }
+    return g;
+}
+
+// half-steps of sweep r (2 per step); sweep r exists iff r <= n - c - 2
+__device__ __forceinline__ int sweep_halfsteps(int n, int b, int c, int r) { return 2 * (1 + (n - 2 - r - c) / b); }
+
+// Right task of one lane: reflector from A[k, p..p+m], applied to rows k+1..p+m of
+// columns p..p+m.  Rows p..p+m (the bottom (m+1)^2 corner) go to the lane's LDS
+// corner for the left task; row k itself is rewritten by the caller after the
+// phase barrier (every wave of the lane has read it by then).  Returns beta.
+template <typename T, int TWM, int NTL>
+__device__ __forceinline__ double right_task(T* __restrict__ A, int64_t S, int S32, StepGeom g,
+                                             typename Compute<T>::type* corner, int ltid) {
     using C = typename Compute<T>::type;
-    constexpr int LDC = TWM + 1;  // leading dimension of the LDS corner block
-    __shared__ C corner[LDC * LDC];
-    __shared__ int s_word[2];
+    constexpr int LDC = TWM + 1;
+    const int k = g.k, p = g.p, m = g.m;
+    const int lane = ltid & (kWave - 1);
+    const int rows = p + m - k;  // rows k+1 .. p+m
+    T* base = A + k + (int64_t)p * S;  // A(k, p)
+    const double xl = static_cast<double>(base[min(lane, m) * S32]);
+    int ri = ltid;
+    C av[TWM + 1];
+    load_row<T, C, TWM>(av, base, S32, 1 + min(ri, rows - 1), m);
+    double vd[TWM + 1], taud, betad;
+    house_uniform<TWM>(xl, m, vd, taud, betad);
+    C vs[TWM + 1];
+#pragma unroll
+    for (int t = 0; t <= TWM; ++t) vs[t] = static_cast<C>(vd[t]);
+    const C tau = static_cast<C>(taud);
+    while (ri < rows) {
+        const int i = k + 1 + ri;
+        if (taud != 0.0) apply_segment<C, TWM>(av, vs, tau, m);
+        if (i >= p) {
+#pragma unroll
+            for (int t = 0; t <= TWM; ++t) corner[(i - p) * LDC + t] = av[t];
+        } else {
+            store_row<T, C, TWM>(av, base, S32, 1 + ri, m);
+        }
+        ri += NTL;
+        if (ri < rows) load_row<T, C, TWM>(av, base, S32, 1 + ri, m);
+    }
+    return betad;
+}
+
+// Left task of one lane: reflector from A[p..p+m, p] (held in the corner), applied
+// to rows p..p+m of columns p+1..L; writes column p as (beta, 0, ..., 0).
+template <typename T, int TWM, int NTL>
+__device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32, StepGeom g, int n, int b,
+                                          const typename Compute<T>::type* corner, int ltid) {
+    using C = typename Compute<T>::type;
+    constexpr int LDC = TWM + 1;
+    const int p = g.p, m = g.m;
+    const int lane = ltid & (kWave - 1);
+    const int L = min(p + m + b, n - 1);
+    const int cols = L - p;  // columns p+1 .. L
+    int ci = ltid;
+    T* base = A + p + (int64_t)p * S;  // A(p, p)
+    C av[TWM + 1];
+    load_col<T, C, TWM>(av, base, S32, corner, min(ci, cols - 1), m);
+    const double xl = static_cast<double>(corner[min(lane, m) * LDC]);
+    double vd[TWM + 1], taud, betad;
+    house_uniform<TWM>(xl, m, vd, taud, betad);
+    C vs[TWM + 1];
+#pragma unroll
+    for (int t = 0; t <= TWM; ++t) vs[t] = static_cast<C>(vd[t]);
+    const C tau = static_cast<C>(taud);
+    while (ci < cols) {
+        if (taud != 0.0) apply_segment<C, TWM>(av, vs, tau, m);
+        store_col<T, C, TWM>(av, base, S32, ci, m);
+        ci += NTL;
+        if (ci < cols) load_col<T, C, TWM>(av, base, S32, corner, ci, m);
+    }
+    if (ltid <= m) base[ltid] = static_cast<T>(ltid == 0 ? betad : 0.0);
+}
+
+// largest workgroup a variant is compiled for (wider windows need more registers)
+template <int TWM>
+constexpr int max_threads() { return TWM >= 16 ? 512 : 1024; }
+
+template <typename T, int TWM, int NTL>
+__global__ __launch_bounds__(max_threads<TWM>()) void bb_stage(StageArgs a) {
+    using C = typename Compute<T>::type;
+    constexpr int LDC = TWM + 1;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C* corners = reinterpret_cast<C*>(smem_raw);  // G blocks of LDC*LDC
+    __shared__ int s_group;
+    __shared__ int s_ok;
 
     const int tid = threadIdx.x;
-    const int lane = tid & (kWave - 1);
+    const int G = blockDim.x / NTL;
+    const int g = tid / NTL;       // lane of this thread
+    const int ltid = tid - g * NTL;
+    C* corner = corners + g * (LDC * LDC);
     T* __restrict__ A = reinterpret_cast<T*>(a.W) + a.uo;
     const int64_t S = a.S;
     const int S32 = (int)a.S;
     const int n = a.n, b = a.b, tw = a.tw, c = a.c, H = a.H;
-    const SyncCtx sc{a.abort_flag, a.err_word, a.spin_limit};
+    const int ngroups = (a.nsweeps + G - 1) / G;
 
     for (;;) {
         if (tid == 0) {
-            int r = atomicAdd(a.claim, 1);
-            if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) r = a.nsweeps;
-            s_word[0] = r;
+            int q = atomicAdd(a.claim, 1);
+            if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) q = ngroups;
+            s_group = q;
         }
         __syncthreads();
-        const int r = s_word[0];
-        if (r >= a.nsweeps) return;
-        const int* prev = r > 0 ? a.progress + (r - 1) : nullptr;
-        int* mine = a.progress + r;
-        const int nsteps = 1 + (n - 2 - r - c) / b;
+        const int q = s_group;
+        if (q >= ngroups) return;
+        const int r0 = q * G;
+        const int nl = min(G, a.nsweeps - r0);  // lanes holding a sweep
+        const int r = r0 + g;
+        const bool has_sweep = g < nl;
+        const int len = has_sweep ? sweep_halfsteps(n, b, c, r) : 0;
+        const int* prev = r0 > 0 ? a.progress + (r0 - 1) : nullptr;
+        int* last = a.progress + (r0 + nl - 1);
+        // phases until every lane finished: lane 0 is the longest-lived (lengths never grow with r)
+        int P_end = 0;
+        for (int l = 0; l < nl; ++l) P_end = max(P_end, sweep_halfsteps(n, b, c, r0 + l) + H * l);
+        const int len_prev = prev ? sweep_halfsteps(n, b, c, r0 - 1) : 0;
+        int known = 0;      // thread 0: last progress value seen for the previous group
+        int published = 0;  // thread 0: last progress value published for this group
 
-        for (int j = 0; j < nsteps; ++j) {
-            int k, p, m;
-            if (j == 0) {
-                k = r;
-                p = r + c;
-                m = min(r + b, n - 1) - p;
-            } else {
-                k = r + c + (j - 1) * b;
-                p = k + b;
-                m = min(tw, n - 1 - p);
-            }
-
-            // ------------------------- right (row) task -------------------------
-            // reflector from A[k, p..p+m]; applied to rows k+1..p+m of columns p..p+m.
-            // Loads are issued before the reflector is formed so their latency overlaps
-            // it; column indices are clamped to p+min(t, m) so every access stays in the
-            // window without per-element branches, and entries t > m are masked to 0.
-            if (prev && !wait_ge(prev, 2 * j + H, sc, &s_word[1])) return;
-            {
-                const int rows = p + m - k;
-                T* base = A + k + (int64_t)p * S;  // A(k, p)
-                const double xl = static_cast<double>(base[min(lane, m) * S32]);
-                int ri = tid;
-                C av[TWM + 1];
-                load_row<T, C, TWM>(av, base, S32, 1 + min(ri, rows - 1), m);
-                double vd[TWM + 1], taud, betad;
-                house_uniform<TWM>(xl, m, vd, taud, betad);
-                C vs[TWM + 1];
-#pragma unroll
-                for (int t = 0; t <= TWM; ++t) vs[t] = static_cast<C>(vd[t]);
-                const C tau = static_cast<C>(taud);
-                while (ri < rows) {
-                    const int i = k + 1 + ri;
-                    if (taud != 0.0) apply_segment<C, TWM>(av, vs, tau, m);
-                    if (i >= p) {  // bottom (m+1) x (m+1) corner stays on chip for the left task
-#pragma unroll
-                        for (int t = 0; t <= TWM; ++t) corner[(i - p) * LDC + t] = av[t];
-                    } else {
-                        store_row<T, C, TWM>(av, base, S32, 1 + ri, m);
+        for (int P = 0; P < P_end; ++P) {
+            // ---- dependency on the previous group (thread 0 polls, then acquires) ----
+            if (tid == 0) {
+                int ok = 1;
+                if (prev) {
+                    int need = 0;
+                    for (int l = 0; l < nl; ++l) {
+                        const int h = P - H * l;
+                        const int ll = sweep_halfsteps(n, b, c, r0 + l);
+                        if (h < 0 || h >= ll) continue;
+                        const int pred_len = l == 0 ? len_prev : sweep_halfsteps(n, b, c, r0 + l - 1);
+                        if (h + H > pred_len) need = kDone;           // predecessor must be DONE
+                        else if (l == 0) need = max(need, h + H);     // lanes > 0 are covered by lock-step
                     }
-                    ri += NT;
-                    if (ri < rows) load_row<T, C, TWM>(av, base, S32, 1 + ri, m);
+                    if (need > known) {
+                        unsigned spins = 0;
+                        int v;
+                        while ((v = __hip_atomic_load(prev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < need) {
+                            __builtin_amdgcn_s_sleep(1);
+                            if ((++spins & 255u) == 0) {
+                                if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                                    ok = 0;
+                                    break;
+                                }
+                                if (spins > a.spin_limit) {
+                                    __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                    __hip_atomic_store(a.err_word, 2 /*BB_ERR_TIMEOUT*/, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_SYSTEM);
+                                    ok = 0;
+                                    break;
+                                }
+                            }
+                        }
+                        known = v;
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    }
                 }
-                // every wave has read row k: now overwrite it with (beta, 0, ..., 0)
-                __syncthreads();
-                if (tid <= m) base[tid * S32] = static_cast<T>(tid == 0 ? betad : 0.0);
-                publish(mine, 2 * j + 1);
+                s_ok = ok;
             }
+            __syncthreads();
+            if (!s_ok) return;
 
-            // ------------------------- left (column) task -------------------------
-            // reflector from A[p..p+m, p]; applied to rows p..p+m of columns p+1..L.
-            // (the corner was completed before the barrier that ended the right task)
-            if (prev && !wait_ge(prev, 2 * j + 1 + H, sc, &s_word[1])) return;
-            {
-                const int L = min(p + m + b, n - 1);
-                const int cols = L - p;  // columns p+1 .. L
-                int ci = tid;
-                T* base = A + p + (int64_t)p * S;  // A(p, p)
-                C av[TWM + 1];
-                load_col<T, C, TWM>(av, base, S32, corner, min(ci, cols - 1), m);
-                const double xl = static_cast<double>(corner[min(lane, m) * LDC]);
-                double vd[TWM + 1], taud, betad;
-                house_uniform<TWM>(xl, m, vd, taud, betad);
-                C vs[TWM + 1];
-#pragma unroll
-                for (int t = 0; t <= TWM; ++t) vs[t] = static_cast<C>(vd[t]);
-                const C tau = static_cast<C>(taud);
-                while (ci < cols) {
-                    if (taud != 0.0) apply_segment<C, TWM>(av, vs, tau, m);
-                    store_col<T, C, TWM>(av, base, S32, ci, m);
-                    ci += NT;
-                    if (ci < cols) load_col<T, C, TWM>(av, base, S32, corner, ci, m);
+            // ---- this phase's half-step of every lane ----
+            const int h = P - H * g;
+            const bool active = has_sweep && h >= 0 && h < len;
+            StepGeom sg{0, 0, 0};
+            double beta_row = 0.0;
+            if (active) {
+                sg = step_geom(n, b, tw, c, r, h >> 1);
+                if ((h & 1) == 0) beta_row = right_task<T, TWM, NTL>(A, S, S32, sg, corner, ltid);
+                else left_task<T, TWM, NTL>(A, S, S32, sg, n, b, corner, ltid);
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();  // every wave of every lane has read its row k
+            if (active && (h & 1) == 0 && ltid <= sg.m)
+                A[sg.k + (int64_t)(sg.p + ltid) * S] = static_cast<T>(ltid == 0 ? beta_row : 0.0);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();  // phase complete: its stores are visible inside the workgroup
+
+            // ---- publish the progress of this group's last sweep ----
+            if (tid == 0) {
+                const int done_last = min(max(P + 1 - H * (nl - 1), 0),
+                                          sweep_halfsteps(n, b, c, r0 + nl - 1));
+                if (done_last > published) {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                    __hip_atomic_store(last, done_last, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    published = done_last;
                 }
-                if (tid <= m) base[tid] = static_cast<T>(tid == 0 ? betad : 0.0);
-                publish(mine, 2 * j + 2);
             }
         }
-        if (prev && !wait_ge(prev, kDone, sc, &s_word[1])) return;
-        if (tid == 0) __hip_atomic_store(mine, kDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();  // s_word reuse by the next claim
+        // ---- all sweeps of the group finished: DONE once the previous group is DONE ----
+        if (tid == 0) {
+            int ok = 1;
+            if (prev && known < kDone) {
+                unsigned spins = 0;
+                while (__hip_atomic_load(prev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < kDone) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if ((++spins & 255u) == 0) {
+                        if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                            ok = 0;
+                            break;
+                        }
+                        if (spins > a.spin_limit) {
+                            __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            __hip_atomic_store(a.err_word, 2 /*BB_ERR_TIMEOUT*/, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_SYSTEM);
+                            ok = 0;
+                            break;
+                        }
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            if (ok) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __hip_atomic_store(last, kDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            s_ok = ok;
+        }
+        __syncthreads();
+        if (!s_ok) return;
     }
 }
 
@@ -402,38 +547,42 @@ hipError_t launch_fill(int* p, int64_t count, int value, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <typename T, int TWM, int NT>
-static hipError_t launch_stage_t(const StageArgs& a, int grid, hipStream_t st) {
-    hipLaunchKernelGGL((bb_stage<T, TWM, NT>), dim3(grid), dim3(NT), 0, st, a);
+template <typename T, int TWM, int NTL>
+static hipError_t launch_stage_t(const StageArgs& a, int lanes, int grid, hipStream_t st) {
+    using C = typename Compute<T>::type;
+    const size_t smem = (size_t)lanes * (TWM + 1) * (TWM + 1) * sizeof(C);
+    hipLaunchKernelGGL((bb_stage<T, TWM, NTL>), dim3(grid), dim3(NTL * lanes), smem, st, a);
     return hipGetLastError();
 }
 
 template <typename T, int TWM>
-static hipError_t launch_stage_nt(const StageArgs& a, int nt, int grid, hipStream_t st) {
-    switch (nt) {
-        case 64: return launch_stage_t<T, TWM, 64>(a, grid, st);
-        case 128: return launch_stage_t<T, TWM, 128>(a, grid, st);
-        case 256: return launch_stage_t<T, TWM, 256>(a, grid, st);
-        case 512: return launch_stage_t<T, TWM, 512>(a, grid, st);
+static hipError_t launch_stage_nt(const StageArgs& a, int ntl, int lanes, int grid, hipStream_t st) {
+    switch (ntl) {
+        case 64: return launch_stage_t<T, TWM, 64>(a, lanes, grid, st);
+        case 128: return launch_stage_t<T, TWM, 128>(a, lanes, grid, st);
+        case 256: return launch_stage_t<T, TWM, 256>(a, lanes, grid, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename T>
-static hipError_t launch_stage_tw(const StageArgs& a, int twm, int nt, int grid, hipStream_t st) {
+static hipError_t launch_stage_tw(const StageArgs& a, int twm, int ntl, int lanes, int grid, hipStream_t st) {
     switch (twm) {
-        case 8: return launch_stage_nt<T, 8>(a, nt, grid, st);
-        case 16: return launch_stage_nt<T, 16>(a, nt, grid, st);
-        case 32: return launch_stage_nt<T, 32>(a, nt, grid, st);
+        case 8: return launch_stage_nt<T, 8>(a, ntl, lanes, grid, st);
+        case 16: return launch_stage_nt<T, 16>(a, ntl, lanes, grid, st);
+        case 32: return launch_stage_nt<T, 32>(a, ntl, lanes, grid, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_stage(int dtype, const StageArgs& a, int twm, int nt, int grid, hipStream_t st) {
+int stage_max_threads(int twm) { return twm >= 16 ? max_threads<16>() : max_threads<8>(); }
+
+hipError_t launch_stage(int dtype, const StageArgs& a, int twm, int ntl, int lanes, int grid, hipStream_t st) {
+    if (lanes < 1 || ntl * lanes > stage_max_threads(twm)) return hipErrorInvalidValue;
     switch (dtype) {
-        case 0: return launch_stage_tw<double>(a, twm, nt, grid, st);
-        case 1: return launch_stage_tw<float>(a, twm, nt, grid, st);
-        default: return launch_stage_tw<_Float16>(a, twm, nt, grid, st);
+        case 0: return launch_stage_tw<double>(a, twm, ntl, lanes, grid, st);
+        case 1: return launch_stage_tw<float>(a, twm, ntl, lanes, grid, st);
+        default: return launch_stage_tw<_Float16>(a, twm, ntl, lanes, grid, st);
     }
 }
 

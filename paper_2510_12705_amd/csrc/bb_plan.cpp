@@ -25,9 +25,11 @@ int default_tw(int dtype) { return dtype == 0 ? 16 : 32; }
 
 int default_threads(int rows) {
     int nt = 64;
-    while (nt < rows && nt < 512) nt *= 2;
+    while (nt < rows && nt < 256) nt *= 2;
     return nt;
 }
+
+int default_lanes(int threads_per_lane) { return std::max(1, std::min(8, 512 / threads_per_lane)); }
 
 int kernel_twm(int tw) { return tw <= 8 ? 8 : tw <= 16 ? 16 : 32; }
 

@@ -30,13 +30,14 @@ int min_lag(int c);
 
 int default_tw(int dtype);
 int default_threads(int rows);
+int default_lanes(int threads_per_lane);
 int kernel_twm(int tw);
 
 // Read + write bytes of the L-shaped window of every step, summed.
 double model_bytes(int64_t n, int64_t b, int elem, int tw);
 
 struct Tuned {
-    int tw, nt, wgs_per_cu;
+    int tw, ntl, lanes, groups_per_cu;
 };
 bool autotune_lookup(int64_t n, int64_t b, int dtype, Tuned* out);
 void autotune_store(int64_t n, int64_t b, int dtype, const Tuned& t);

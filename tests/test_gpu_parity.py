@@ -87,26 +87,26 @@ def test_ragged_fp64_parity(bb, n, b, tw):
     check_fp64(band, n, b, tw, d, e)
 
 
-@pytest.mark.parametrize("nt", [64, 128, 256, 512])
-def test_thread_counts_are_bitwise_identical(bb, nt):
-    """Every thread count computes the same per-row/per-column arithmetic."""
+@pytest.mark.parametrize("ntl,lanes", [(64, 1), (64, 4), (128, 2), (128, 8), (256, 1), (256, 4)])
+def test_thread_and_lane_counts_are_bitwise_identical(bb, ntl, lanes):
+    """Every thread count and group size computes the same per-row/per-column arithmetic."""
     n, b, tw = 700, 48, 16
     band = inputs.band_normal(n, b, seed=3)
-    ref = gpu_reduce(bb, band, n, b, tw=tw, threads_per_window=256)
-    d, e = gpu_reduce(bb, band, n, b, tw=tw, threads_per_window=nt)
+    ref = gpu_reduce(bb, band, n, b, tw=tw, threads_per_window=128, sweeps_per_group=1)
+    d, e = gpu_reduce(bb, band, n, b, tw=tw, threads_per_window=ntl, sweeps_per_group=lanes)
     assert np.array_equal(d, ref[0]) and np.array_equal(e, ref[1])
 
 
-@pytest.mark.parametrize("spc", [1, 2, 16])
-def test_schedule_independence_bitwise(bb, spc):
-    """Race detector: concurrently running tasks are disjoint, so the grid size
-    (how many sweeps are in flight) must not change a single bit."""
+@pytest.mark.parametrize("gpc,lanes", [(1, 1), (2, 3), (16, 2), (1, 8)])
+def test_schedule_independence_bitwise(bb, gpc, lanes):
+    """Race detector: concurrently running tasks are disjoint, so how many sweeps are in
+    flight (groups per CU, sweeps per group) must not change a single bit."""
     n, b, tw = 3000, 64, 16
     band = inputs.band_normal(n, b, seed=4)
-    ref = gpu_reduce(bb, band, n, b, tw=tw, sweeps_per_cu=8)
-    again = gpu_reduce(bb, band, n, b, tw=tw, sweeps_per_cu=8)
+    ref = gpu_reduce(bb, band, n, b, tw=tw)
+    again = gpu_reduce(bb, band, n, b, tw=tw)
     assert np.array_equal(again[0], ref[0]) and np.array_equal(again[1], ref[1])
-    d, e = gpu_reduce(bb, band, n, b, tw=tw, sweeps_per_cu=spc)
+    d, e = gpu_reduce(bb, band, n, b, tw=tw, groups_per_cu=gpc, sweeps_per_group=lanes)
     assert np.array_equal(d, ref[0]) and np.array_equal(e, ref[1])
 
 
