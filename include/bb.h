@@ -99,6 +99,13 @@ int bb_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void *band, int64_t 
  * bb_reduce.  Argument numbers: count=1, n=2, b=3, dtype=4, band=5, ldband=6,
  * d=7, e=8.  A matrix with an invalid entry makes the whole call fail with
  * the argument number of the array, before any work is enqueued.
+ * The first call for a given (count, n[], b[], dtype, parameters, stream)
+ * builds a plan and allocates its device workspace (hipMalloc); later calls
+ * with the same key reuse it and allocate nothing, so they may be captured
+ * into a hipGraph (the captured copy of the pointer arrays reads them from a
+ * pinned host buffer at replay time: replays use the pointers of the most
+ * recent call with that key).  Calls sharing a plan must not overlap in time;
+ * bb_release() frees all plans.
  */
 int bb_reduce_batched(int64_t count, const int64_t *n, const int64_t *b, bb_dtype_t dtype,
                       const void *const *band, const int64_t *ldband,

@@ -38,6 +38,10 @@ class Params(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("HIP library %s is not built (run __graft_entry__.build())" % LIB_PATH)
+    # torch ships its own HIP runtime under the same soname as the system one; it
+    # must be loaded first so that the library binds to it and both share one
+    # runtime (device memory and streams come from torch).
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     i64, vp, dp, ip = ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
     lib.bb_reduce.argtypes = [i64, i64, ctypes.c_int, vp, i64, vp, vp, vp]

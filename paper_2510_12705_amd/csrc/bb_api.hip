@@ -105,6 +105,9 @@ struct Workspace {
     size_t band_bytes = 0, counter_bytes = 0, total = 0;
     int64_t ldw = 0, uo = 0, max_sweeps = 0;
     int nstages = 0;
+    // counter words: progress[nstages][max_sweeps] | claim, abort per stage | FP16
+    // amax per stage | FP16 exps[nstages + 1]; all zero-initialised per call
+    int64_t off_claim = 0, off_amax = 0, off_exps = 0, ncounters = 0;
 };
 
 Workspace workspace_layout(int64_t n, int64_t b, int dtype, int tw) {
@@ -116,15 +119,220 @@ Workspace workspace_layout(int64_t n, int64_t b, int dtype, int tw) {
     w.nstages = (int)plan.stages.size();
     w.max_sweeps = std::max<int64_t>(n, 1);
     w.band_bytes = align_up((size_t)(n * w.ldw) * elem_size(dtype), 256);
-    // per stage: progress[max_sweeps]; then claim + abort words per stage; then the
-    // FP16 scale words (amax, exps[nstages + 1])
-    w.counter_bytes =
-        align_up(sizeof(int) * (size_t)(w.nstages * w.max_sweeps + 2 * w.nstages + 2 + w.nstages + 2), 256);
+    w.off_claim = w.nstages * w.max_sweeps;
+    w.off_amax = w.off_claim + 2 * w.nstages;
+    w.off_exps = w.off_amax + w.nstages;
+    w.ncounters = w.off_exps + w.nstages + 1;
+    w.counter_bytes = align_up(sizeof(int) * (size_t)w.ncounters, 256);
     w.total = w.band_bytes + w.counter_bytes;
     return w;
 }
 
 int check_hip(hipError_t e) { return e == hipSuccess ? BB_OK : BB_ERR_HIP; }
+
+// ---------------------------------------------------------------------------
+// Ragged batch plan, cached per (shapes, dtype, launch parameters, stream): the
+// device workspace is allocated once with hipMalloc and reused, so repeated
+// calls allocate nothing and can be captured into a hipGraph.  Calls that share
+// a plan must not overlap in time (they share its workspace); calls on
+// different streams get different plans.
+// ---------------------------------------------------------------------------
+struct BatchPlan {
+    uint64_t key = 0;
+    hipStream_t stream = nullptr;
+    int count = 0, dtype = 0, tw = 0, ntl = 0, lanes = 0, twm = 0;
+    int64_t max_elems = 0, max_n = 0;
+    int ntasks = 0, nprogress = 0, nexps = 0;
+    std::vector<bbk::BatchMatrix> mats;
+    std::vector<bbk::BatchStage> stages;
+    std::vector<bbk::BatchTask> tasks;
+    char* dev = nullptr;   // device workspace
+    size_t dev_bytes = 0;
+    size_t off_counters = 0, off_mats = 0, off_stages = 0, off_tasks = 0, off_ptrs = 0;
+    int64_t ncounters = 0;
+    void* pinned = nullptr;  // staging for the per-call pointer arrays
+    hipEvent_t staged = nullptr;
+    bool staged_pending = false;
+};
+
+std::vector<BatchPlan*> g_batch_plans;
+
+uint64_t mix(uint64_t h, uint64_t v) {
+    h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+    return h;
+}
+
+int batch_plan(int64_t count, const int64_t* n, const int64_t* b, int dtype, const Launch& L, hipStream_t st,
+               BatchPlan** out) {
+    uint64_t key = mix(mix(mix(mix(mix(0, (uint64_t)count), (uint64_t)dtype), (uint64_t)L.tw), (uint64_t)L.ntl),
+                       (uint64_t)L.lanes);
+    for (int64_t i = 0; i < count; ++i) key = mix(mix(key, (uint64_t)n[i]), (uint64_t)b[i]);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (BatchPlan* p : g_batch_plans)
+            if (p->key == key && p->stream == st) {
+                *out = p;
+                return BB_OK;
+            }
+    }
+    BatchPlan* P = new BatchPlan();
+    P->key = key;
+    P->stream = st;
+    P->count = (int)count;
+    P->dtype = dtype;
+    P->tw = L.tw;
+    P->ntl = L.ntl;
+    P->lanes = L.lanes;
+    P->twm = bbp::kernel_twm(L.tw);
+    size_t band_off = 0;
+    std::vector<size_t> band_offs((size_t)count);
+    int max_stages = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        bbk::BatchMatrix M{};
+        const int64_t bb = n[i] > 0 ? std::min<int64_t>(b[i], n[i] - 1) : 0;
+        Workspace w = workspace_layout(std::max<int64_t>(n[i], 1), bb, dtype, L.tw);
+        bbp::Plan pl = bbp::make_plan(bb, L.tw);
+        M.S = w.ldw - 1;
+        M.uo = w.uo;
+        M.n = (int)n[i];
+        M.b = (int)bb;
+        M.b_in = (int)b[i];
+        M.nstages = (int)pl.stages.size();
+        M.stage_off = (int)P->stages.size();
+        M.exp_off = P->nexps;
+        P->nexps += M.nstages + 1;
+        band_offs[(size_t)i] = band_off;
+        band_off += w.band_bytes;
+        P->max_elems = std::max<int64_t>(P->max_elems, (int64_t)n[i] * w.ldw);
+        P->max_n = std::max<int64_t>(P->max_n, n[i]);
+        for (const bbp::Stage& sg : pl.stages) {
+            bbk::BatchStage S{};
+            S.b = sg.b;
+            S.tw = sg.tw;
+            S.c = sg.c;
+            S.H = std::max(sg.lag, L.lag);
+            S.nsweeps = (int)std::max<int64_t>(n[i] - sg.c - 1, 0);
+            S.ngroups = (S.nsweeps + L.lanes - 1) / L.lanes;
+            S.prog_off = P->nprogress;
+            P->nprogress += S.ngroups;
+            P->stages.push_back(S);
+        }
+        max_stages = std::max(max_stages, M.nstages);
+        P->mats.push_back(M);
+    }
+    // tasks ordered by (stage, group, matrix): every dependency precedes its task
+    for (int sidx = 0; sidx < max_stages; ++sidx) {
+        int max_groups = 0;
+        for (const auto& M : P->mats)
+            if (sidx < M.nstages) max_groups = std::max(max_groups, P->stages[M.stage_off + sidx].ngroups);
+        for (int q = 0; q < max_groups; ++q)
+            for (int i = 0; i < P->count; ++i) {
+                const auto& M = P->mats[i];
+                if (sidx < M.nstages && q < P->stages[M.stage_off + sidx].ngroups)
+                    P->tasks.push_back(bbk::BatchTask{i, sidx, q});
+            }
+    }
+    P->ntasks = (int)P->tasks.size();
+    // device layout: bands | counters (progress, exps, claim, abort) | mats | stages | tasks | pointer arrays
+    P->ncounters = (int64_t)P->nprogress + P->nexps + 2;
+    P->off_counters = align_up(band_off, 256);
+    P->off_mats = align_up(P->off_counters + sizeof(int) * (size_t)P->ncounters, 256);
+    P->off_stages = align_up(P->off_mats + sizeof(bbk::BatchMatrix) * P->mats.size(), 256);
+    P->off_tasks = align_up(P->off_stages + sizeof(bbk::BatchStage) * std::max<size_t>(P->stages.size(), 1), 256);
+    P->off_ptrs = align_up(P->off_tasks + sizeof(bbk::BatchTask) * std::max<size_t>(P->tasks.size(), 1), 256);
+    P->dev_bytes = P->off_ptrs + 4 * sizeof(void*) * (size_t)count;
+    if (hipMalloc((void**)&P->dev, P->dev_bytes) != hipSuccess) {
+        delete P;
+        return BB_ERR_NOMEM;
+    }
+    for (int64_t i = 0; i < count; ++i) P->mats[(size_t)i].W = P->dev + band_offs[(size_t)i];
+    if (hipHostMalloc(&P->pinned, 4 * sizeof(void*) * (size_t)count, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&P->staged, hipEventDisableTiming) != hipSuccess) {
+        (void)hipFree(P->dev);
+        delete P;
+        return BB_ERR_NOMEM;
+    }
+    // static metadata: one synchronous upload when the plan is built
+    if (hipMemcpy(P->dev + P->off_mats, P->mats.data(), sizeof(bbk::BatchMatrix) * P->mats.size(),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        (!P->stages.empty() && hipMemcpy(P->dev + P->off_stages, P->stages.data(),
+                                         sizeof(bbk::BatchStage) * P->stages.size(), hipMemcpyHostToDevice) != hipSuccess) ||
+        (!P->tasks.empty() && hipMemcpy(P->dev + P->off_tasks, P->tasks.data(), sizeof(bbk::BatchTask) * P->tasks.size(),
+                                        hipMemcpyHostToDevice) != hipSuccess)) {
+        (void)hipFree(P->dev);
+        delete P;
+        return BB_ERR_HIP;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_batch_plans.push_back(P);
+    *out = P;
+    return BB_OK;
+}
+
+int batch_run(BatchPlan* P, DeviceState* ds, const void* const* band, const int64_t* ldband, double* const* d,
+              double* const* e, const Launch& L, hipStream_t st) {
+    const size_t cnt = (size_t)P->count;
+    // The staging buffer may still feed the previous call's copy.  While the stream
+    // is being captured into a graph nothing is executed, and the captured copy
+    // reads the staging buffer when the graph is replayed.
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) return BB_ERR_HIP;
+    const bool capturing = cs != hipStreamCaptureStatusNone;
+    if (!capturing && P->staged_pending && hipEventSynchronize(P->staged) != hipSuccess) return BB_ERR_HIP;
+    void** host = static_cast<void**>(P->pinned);
+    for (size_t i = 0; i < cnt; ++i) {
+        host[i] = const_cast<void*>(band[i]);
+        host[cnt + i] = reinterpret_cast<void*>(ldband[i]);
+        host[2 * cnt + i] = d[i];
+        host[3 * cnt + i] = e[i];
+    }
+    char* ptrs = P->dev + P->off_ptrs;
+    int rc = check_hip(hipMemcpyAsync(ptrs, host, 4 * sizeof(void*) * cnt, hipMemcpyHostToDevice, st));
+    if (!rc && !capturing) {
+        rc = check_hip(hipEventRecord(P->staged, st));
+        P->staged_pending = rc == BB_OK;
+    }
+    int* counters = reinterpret_cast<int*>(P->dev + P->off_counters);
+    const auto* mats = reinterpret_cast<const bbk::BatchMatrix*>(P->dev + P->off_mats);
+    if (!rc) rc = check_hip(bbk::launch_fill(counters, P->ncounters, 0, st));
+    if (!rc)
+        rc = check_hip(bbk::launch_pack_batched(P->dtype, mats, P->count, P->max_elems,
+                                                reinterpret_cast<const void* const*>(ptrs),
+                                                reinterpret_cast<const int64_t*>(ptrs + sizeof(void*) * cnt), st));
+    if (!rc && P->ntasks > 0) {
+        bbk::BatchArgs a;
+        a.mats = mats;
+        a.stages = reinterpret_cast<const bbk::BatchStage*>(P->dev + P->off_stages);
+        a.tasks = reinterpret_cast<const bbk::BatchTask*>(P->dev + P->off_tasks);
+        a.ntasks = P->ntasks;
+        a.progress = counters;
+        a.exps = counters + P->nprogress;
+        a.claim = counters + P->nprogress + P->nexps;
+        a.abort_flag = a.claim + 1;
+        a.err_word = ds->err_dev;
+        a.spin_limit = spin_limit();
+        const int grid = (int)std::min<int64_t>(P->ntasks, (int64_t)ds->cus * L.groups_per_cu);
+        rc = check_hip(bbk::launch_batched(P->dtype, a, P->twm, P->ntl, P->lanes, grid, st));
+    }
+    if (!rc)
+        rc = check_hip(bbk::launch_extract_batched(P->dtype, mats, P->count, P->max_n,
+                                                   P->dtype == BB_F16 ? counters + P->nprogress : nullptr,
+                                                   reinterpret_cast<double* const*>(ptrs + 2 * sizeof(void*) * cnt),
+                                                   reinterpret_cast<double* const*>(ptrs + 3 * sizeof(void*) * cnt), st));
+    return rc;
+}
+
+void batch_plans_clear() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (BatchPlan* p : g_batch_plans) {
+        if (p->staged_pending) (void)hipEventSynchronize(p->staged);
+        (void)hipEventDestroy(p->staged);
+        (void)hipHostFree(p->pinned);
+        (void)hipFree(p->dev);
+        delete p;
+    }
+    g_batch_plans.clear();
+}
 
 }  // namespace
 
@@ -157,9 +365,9 @@ int bb_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, int64_t 
     if (hipMallocAsync(&base, ws.total, st) != hipSuccess) return BB_ERR_NOMEM;
     char* W = (char*)base;
     int* counters = (int*)((char*)base + ws.band_bytes);
-    const int64_t ncounters = ws.nstages * ws.max_sweeps + 2 * ws.nstages + 2 + ws.nstages + 2;
-    unsigned* f16_amax = (unsigned*)(counters + ws.nstages * ws.max_sweeps + 2 * ws.nstages + 2);
-    int* f16_exps = (int*)(f16_amax + 1);  // nstages + 1 exponents, zero-initialised
+    const int64_t ncounters = ws.ncounters;
+    unsigned* f16_amax = (unsigned*)(counters + ws.off_amax);  // one word per stage
+    int* f16_exps = counters + ws.off_exps;                     // nstages + 1 exponents
 
     float scale = 1.0f;
     double inv_scale = 1.0;
@@ -178,13 +386,13 @@ int bb_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, int64_t 
         a.H = std::max(sg.lag, L.lag);
         a.nsweeps = (int)std::max<int64_t>(n - sg.c - 1, 0);
         a.progress = counters + s * ws.max_sweeps;
-        a.claim = counters + ws.nstages * ws.max_sweeps + 2 * s;
+        a.claim = counters + ws.off_claim + 2 * s;
         a.abort_flag = a.claim + 1;
         a.err_word = ds->err_dev;
         a.spin_limit = spin_limit();
         if (a.nsweeps == 0) continue;
         if (dtype == BB_F16)
-            rc = check_hip(bbk::launch_f16_rescale(W, n * ws.ldw, f16_amax, f16_exps, s, st));
+            rc = check_hip(bbk::launch_f16_rescale(W, n * ws.ldw, f16_amax + s, f16_exps, s, st));
         if (rc) break;
         const int twm = bbp::kernel_twm(sg.tw);
         const int64_t ngroups = (a.nsweeps + L.lanes - 1) / L.lanes;
@@ -219,8 +427,9 @@ int bb_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, int64_t 
 
 int bb_reduce_batched(int64_t count, const int64_t* n, const int64_t* b, bb_dtype_t dtype, const void* const* band,
                       const int64_t* ldband, double* const* d, double* const* e, void* stream) {
-    if (count < 0) return -1;
-    if (count > 0 && (!n || !b || !band || !ldband || !d || !e)) return !n ? -2 : !b ? -3 : !band ? -5 : !ldband ? -6 : !d ? -7 : -8;
+    if (count < 0 || count > (1 << 20)) return -1;
+    if (count > 0 && (!n || !b || !band || !ldband || !d || !e))
+        return !n ? -2 : !b ? -3 : !band ? -5 : !ldband ? -6 : !d ? -7 : -8;
     if (dtype != BB_F64 && dtype != BB_F32 && dtype != BB_F16) return -4;
     for (int64_t i = 0; i < count; ++i) {
         if (n[i] < 0 || n[i] > (int64_t)1 << 30) return -2;
@@ -230,11 +439,22 @@ int bb_reduce_batched(int64_t count, const int64_t* n, const int64_t* b, bb_dtyp
         if (n[i] > 0 && !d[i]) return -7;
         if (n[i] > 1 && !e[i]) return -8;
     }
+    if (count == 0) return BB_OK;
+    hipStream_t st = (hipStream_t)stream;
+    DeviceState* ds = nullptr;
+    int rc = device_state(&ds);
+    if (rc) return rc;
+    int64_t max_n = 0, max_b = 0;
     for (int64_t i = 0; i < count; ++i) {
-        int rc = bb_reduce(n[i], b[i], dtype, band[i], ldband[i], d[i], e[i], stream);
-        if (rc) return rc;
+        max_n = std::max(max_n, n[i]);
+        max_b = std::max(max_b, std::min(b[i], std::max<int64_t>(n[i] - 1, 0)));
     }
-    return BB_OK;
+    Launch L = resolve(max_n, max_b, dtype);
+    if (L.tw < 1 || L.tw > bbp::kMaxTW) return BB_ERR_UNSUPPORTED;
+    BatchPlan* bp = nullptr;
+    rc = batch_plan(count, n, b, dtype, L, st, &bp);
+    if (rc) return rc;
+    return batch_run(bp, ds, band, ldband, d, e, L, st);
 }
 
 int bb_set_params(const bb_params_t* p) {
@@ -329,6 +549,7 @@ int bb_timing_read(double* stage_ms, int64_t* stage_launches) {
 
 int bb_release(void) {
     bbp::autotune_clear();
+    batch_plans_clear();
     return BB_OK;
 }
 

@@ -105,24 +105,6 @@ __device__ __forceinline__ double nrm2_lanes_general(double xm, int m, int knt) 
     return nrm2_finish(notbig, asml, amed, abig);
 }
 
-// xNRM2 of x[1..m] (x[t] == 0 for t > m).  When every nonzero |x_t| lies in
-// [tsml, tbig] it reduces to sqrt of the plain left-to-right sum of squares
-// (zeros add exactly +0); otherwise the general algorithm runs on the lanes.
-template <int TWM>
-__device__ __forceinline__ double nrm2_uniform(const double (&x)[TWM + 1], double xm, int m) {
-    constexpr double tsml = 0x1p-511, tbig = 0x1p486;
-    bool mid = true;
-    double amed = 0.0;
-#pragma unroll
-    for (int t = 1; t <= TWM; ++t) {
-        const double ax = fabs(x[t]);
-        mid = mid & ((ax == 0.0) | ((ax >= tsml) & (ax <= tbig)));
-        amed = amed + ax * ax;
-    }
-    if (mid) return sqrt(amed);
-    return nrm2_lanes_general(xm, m, 0);
-}
-
 __device__ __forceinline__ double lapy2(double a, double b) {
     const double xa = fabs(a), ya = fabs(b);
     const double w = xa > ya ? xa : ya, z = xa < ya ? xa : ya;
@@ -132,20 +114,30 @@ __device__ __forceinline__ double lapy2(double a, double b) {
 }
 
 // x_lane: lane t (0 <= t <= m) holds x_t.  On return v[0..TWM] holds the
-// reflector (v[0] = 1, v[t] = 0 for t > m), uniform across the wave.
-template <int TWM>
-__device__ __forceinline__ void house_uniform(double x_lane, int m, double (&v)[TWM + 1], double& tau,
-                                              double& beta) {
-    double x[TWM + 1];
-    const double xm = mask_above(x_lane, m);
+// reflector (v[0] = 1, v[t] = 0 for t > m), uniform across the wave.  The lane
+// values are re-read with readlane where needed rather than kept in an array,
+// which keeps register pressure low for wide windows.
+template <int TWM, typename V>
+__device__ __forceinline__ void house_uniform(double x_lane, int m, V (&v)[TWM + 1], double& tau, double& beta) {
+    constexpr double tsml = 0x1p-511, tbig = 0x1p486;
+    const double xm = mask_above(x_lane, m);  // lanes above m hold +0
+    double alpha = readlane_f64(xm, 0);
+    // xNRM2 of x2: when every nonzero |x_t| lies in [tsml, tbig] it is the square
+    // root of the plain left-to-right sum of squares (zeros add exactly +0);
+    // otherwise the general algorithm runs over the lanes.
+    bool mid = true;
+    double amed = 0.0;
 #pragma unroll
-    for (int t = 0; t <= TWM; ++t) x[t] = readlane_f64(xm, t);
-    double alpha = x[0];
-    double xn = nrm2_uniform<TWM>(x, xm, m);
-    v[0] = 1.0;
+    for (int t = 1; t <= TWM; ++t) {
+        const double ax = fabs(readlane_f64(xm, t));
+        mid = mid & ((ax == 0.0) | ((ax >= tsml) & (ax <= tbig)));
+        amed = amed + ax * ax;
+    }
+    double xn = mid ? sqrt(amed) : nrm2_lanes_general(xm, m, 0);
+    v[0] = V(1);
     if (xn == 0.0) {
 #pragma unroll
-        for (int t = 1; t <= TWM; ++t) v[t] = 0.0;
+        for (int t = 1; t <= TWM; ++t) v[t] = V(0);
         tau = 0.0;
         beta = alpha;
         return;
@@ -153,25 +145,24 @@ __device__ __forceinline__ void house_uniform(double x_lane, int m, double (&v)[
     double h = lapy2(alpha, xn);
     double bt = alpha >= 0.0 ? -h : h;
     constexpr double safmin = 2.2250738585072014e-308 / 2.220446049250313e-16;  // DBL_MIN / DBL_EPSILON
+    constexpr double rsafmn = 1.0 / safmin;
     int knt = 0;
     if (fabs(bt) < safmin) {
-        constexpr double rsafmn = 1.0 / safmin;
         do {
             ++knt;
             bt = bt * rsafmn;
             alpha = alpha * rsafmn;
         } while (fabs(bt) < safmin && knt < 20);
-        for (int i = 0; i < knt; ++i) {
-#pragma unroll
-            for (int t = 1; t <= TWM; ++t) x[t] = x[t] * rsafmn;  // exact power-of-two scaling
-        }
         xn = nrm2_lanes_general(xm, m, knt);
         h = lapy2(alpha, xn);
         bt = alpha >= 0.0 ? -h : h;
     }
     const double scal = 1.0 / (alpha - bt);
+    double xs = xm;  // this lane's x_t, rescaled like the reference (exact powers of two)
+#pragma unroll 1
+    for (int i = 0; i < knt; ++i) xs = xs * rsafmn;
 #pragma unroll
-    for (int t = 1; t <= TWM; ++t) v[t] = x[t] * scal;  // x[t] == 0 for t > m
+    for (int t = 1; t <= TWM; ++t) v[t] = static_cast<V>(readlane_f64(xs, t) * scal);  // x_t == 0 for t > m
     tau = (bt - alpha) / bt;
     for (int i = 0; i < knt; ++i) bt = bt * safmin;
     beta = bt;

@@ -21,6 +21,43 @@ struct StageArgs {
     unsigned spin_limit;
 };
 
+// ---- ragged batch ----
+struct BatchStage {
+    int b, tw, c, H;   // stage geometry and half-step lag
+    int nsweeps;       // n - c - 1
+    int ngroups;       // groups of consecutive sweeps
+    int prog_off;      // offset of this stage's group progress words
+};
+struct BatchMatrix {
+    void* W;           // working band (element type = storage type)
+    int64_t S;         // ld_w - 1
+    int64_t uo;        // diagonal offset in a band column
+    int n, b, b_in;    // order, clamped bandwidth, caller's bandwidth (band indexing)
+    int nstages;
+    int stage_off;     // index of the first BatchStage of this matrix
+    int exp_off;       // FP16: index of this matrix's nstages + 1 scale exponents
+};
+struct BatchTask {
+    int matrix, stage, group;
+};
+struct BatchArgs {
+    const BatchMatrix* mats;
+    const BatchStage* stages;
+    const BatchTask* tasks;
+    int ntasks;
+    int* progress;     // all group progress words (zeroed before launch)
+    int* exps;         // FP16 scale exponents (zeroed before launch)
+    int* claim;
+    int* abort_flag;
+    int* err_word;
+    unsigned spin_limit;
+};
+hipError_t launch_batched(int dtype, const BatchArgs& a, int twm, int ntl, int lanes, int grid, hipStream_t st);
+hipError_t launch_pack_batched(int dtype, const BatchMatrix* mats, int count, int64_t max_elems,
+                               const void* const* bands, const int64_t* ldbands, hipStream_t st);
+hipError_t launch_extract_batched(int dtype, const BatchMatrix* mats, int count, int64_t max_n, const int* exps,
+                                  double* const* ds, double* const* es, hipStream_t st);
+
 hipError_t launch_pack(int dtype, const void* band, int64_t ldband, int64_t n, int64_t b_in, int64_t b, void* W,
                        int64_t ldw, int64_t uo, float scale, hipStream_t st);
 hipError_t launch_extract(int dtype, const void* W, int64_t n, int64_t ldw, int64_t uo, double inv_scale, double* d,

@@ -276,11 +276,9 @@ __device__ __forceinline__ double right_task(T* __restrict__ A, int64_t S, int S
     int ri = ltid;
     C av[TWM + 1];
     load_row<T, C, TWM>(av, base, S32, 1 + min(ri, rows - 1), m);
-    double vd[TWM + 1], taud, betad;
-    house_uniform<TWM>(xl, m, vd, taud, betad);
     C vs[TWM + 1];
-#pragma unroll
-    for (int t = 0; t <= TWM; ++t) vs[t] = static_cast<C>(vd[t]);
+    double taud, betad;
+    house_uniform<TWM>(xl, m, vs, taud, betad);
     const C tau = static_cast<C>(taud);
     while (ri < rows) {
         const int i = k + 1 + ri;
@@ -313,11 +311,9 @@ __device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32,
     C av[TWM + 1];
     load_col<T, C, TWM>(av, base, S32, corner, min(ci, cols - 1), m);
     const double xl = static_cast<double>(corner[min(lane, m) * LDC]);
-    double vd[TWM + 1], taud, betad;
-    house_uniform<TWM>(xl, m, vd, taud, betad);
     C vs[TWM + 1];
-#pragma unroll
-    for (int t = 0; t <= TWM; ++t) vs[t] = static_cast<C>(vd[t]);
+    double taud, betad;
+    house_uniform<TWM>(xl, m, vs, taud, betad);
     const C tau = static_cast<C>(taud);
     while (ci < cols) {
         if (taud != 0.0) apply_segment<C, TWM>(av, vs, tau, m);
@@ -332,28 +328,160 @@ __device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32,
 template <int TWM>
 constexpr int max_threads() { return TWM >= 16 ? 512 : 1024; }
 
+// Thread 0 only: spin until *flag >= need (or abort / watchdog).  Returns the value
+// seen (>= need) or -1 on abort; ends with an agent-scope acquire.
+__device__ __forceinline__ int poll_ge(const int* flag, int need, int* abort_flag, int* err_word, unsigned spin_limit) {
+    unsigned spins = 0;
+    int v;
+    while ((v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < need) {
+        __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 255u) == 0) {
+            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return -1;
+            if (spins > spin_limit) {
+                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(err_word, 2 /*BB_ERR_TIMEOUT*/, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                return -1;
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return v;
+}
+
+// One group of consecutive sweeps r0 .. r0+nl-1 of one stage.
+struct GroupArgs {
+    void* A;                 // working band base + uo (element type T)
+    int64_t S;               // ld_w - 1
+    int n, b, tw, c, H;      // stage geometry and half-step lag
+    int nsweeps;             // sweeps of the stage
+    int r0;                  // first sweep of the group
+    const int* prev;         // progress word of the previous group of this stage (null: none)
+    const int* stage_prev;   // progress word of the last group of the previous stage; must be
+                             // DONE before phase 0 (null: no wait)
+    int* last;               // this group's progress word
+    int* abort_flag;
+    int* err_word;
+    unsigned spin_limit;
+};
+
+// Executed by the whole workgroup (G lanes of NTL threads).  In phase P lane g
+// runs half-step P - H*g of sweep r0+g; see bb_stage below.  Returns false if the
+// pipeline was aborted.
+template <typename T, int TWM, int NTL>
+__device__ bool run_group(const GroupArgs& ga, typename Compute<T>::type* corners, int* s_ok) {
+    using C = typename Compute<T>::type;
+    constexpr int LDC = TWM + 1;
+    const int tid = threadIdx.x;
+    const int G = blockDim.x / NTL;
+    const int g = tid / NTL;
+    const int ltid = tid - g * NTL;
+    C* corner = corners + g * (LDC * LDC);
+    T* __restrict__ A = reinterpret_cast<T*>(ga.A);
+    const int64_t S = ga.S;
+    const int S32 = (int)ga.S;
+    const int n = ga.n, b = ga.b, tw = ga.tw, c = ga.c, H = ga.H;
+    const int r0 = ga.r0;
+    const int nl = min(G, ga.nsweeps - r0);
+    const int r = r0 + g;
+    const bool has_sweep = g < nl;
+    const int len = has_sweep ? sweep_halfsteps(n, b, c, r) : 0;
+    // lengths never grow with r, so lane 0 finishes last among the lanes of equal
+    // length; phases run until every lane finished
+    int P_end = 0;
+    for (int l = 0; l < nl; ++l) P_end = max(P_end, sweep_halfsteps(n, b, c, r0 + l) + H * l);
+    const int len_prev = ga.prev ? sweep_halfsteps(n, b, c, r0 - 1) : 0;
+    const int len_last = sweep_halfsteps(n, b, c, r0 + nl - 1);
+    int known = 0;      // thread 0: progress value last seen for the previous group
+    int published = 0;  // thread 0: progress value last published for this group
+
+    if (tid == 0) {
+        int ok = 1;
+        if (ga.stage_prev && poll_ge(ga.stage_prev, kDone, ga.abort_flag, ga.err_word, ga.spin_limit) < 0) ok = 0;
+        *s_ok = ok;
+    }
+    // (the first phase's barrier publishes *s_ok)
+
+    for (int P = 0; P < P_end; ++P) {
+        // ---- dependency on the previous group (thread 0 polls, then acquires) ----
+        if (tid == 0 && *s_ok && ga.prev) {
+            int need = 0;
+            for (int l = 0; l < nl; ++l) {
+                const int h = P - H * l;
+                const int ll = sweep_halfsteps(n, b, c, r0 + l);
+                if (h < 0 || h >= ll) continue;
+                const int pred_len = l == 0 ? len_prev : sweep_halfsteps(n, b, c, r0 + l - 1);
+                if (h + H > pred_len) need = kDone;        // predecessor must be DONE
+                else if (l == 0) need = max(need, h + H);  // lanes > 0 are covered by lock-step
+            }
+            if (need > known) {
+                const int v = poll_ge(ga.prev, need, ga.abort_flag, ga.err_word, ga.spin_limit);
+                if (v < 0) *s_ok = 0;
+                else known = v;
+            }
+        }
+        __syncthreads();
+        if (!*s_ok) return false;
+
+        // ---- this phase's half-step of every lane ----
+        const int h = P - H * g;
+        const bool active = has_sweep && h >= 0 && h < len;
+        StepGeom sg{0, 0, 0};
+        double beta_row = 0.0;
+        if (active) {
+            sg = step_geom(n, b, tw, c, r, h >> 1);
+            if ((h & 1) == 0) beta_row = right_task<T, TWM, NTL>(A, S, S32, sg, corner, ltid);
+            else left_task<T, TWM, NTL>(A, S, S32, sg, n, b, corner, ltid);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();  // every wave of every lane has read its row k
+        if (active && (h & 1) == 0 && ltid <= sg.m)
+            A[sg.k + (int64_t)(sg.p + ltid) * S] = static_cast<T>(ltid == 0 ? beta_row : 0.0);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();  // phase complete: its stores are visible inside the workgroup
+
+        // ---- publish the progress of this group's last sweep ----
+        if (tid == 0) {
+            const int done_last = min(max(P + 1 - H * (nl - 1), 0), len_last);
+            if (done_last > published) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __hip_atomic_store(ga.last, done_last, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                published = done_last;
+            }
+        }
+    }
+    // ---- all sweeps of the group finished: DONE once the previous group is DONE ----
+    if (tid == 0) {
+        int ok = *s_ok;
+        if (ok && ga.prev && known < kDone && poll_ge(ga.prev, kDone, ga.abort_flag, ga.err_word, ga.spin_limit) < 0)
+            ok = 0;
+        if (ok) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_store(ga.last, kDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        *s_ok = ok;
+    }
+    __syncthreads();
+    return *s_ok != 0;
+}
+
+// ---------------------------------------------------------------------------
+// One bandwidth-reduction stage of one band.  Workgroups claim groups of G
+// consecutive sweeps in order (group q depends only on group q-1, claimed
+// earlier by a running workgroup, so the claim order cannot deadlock).
+// progress[q] is group q's word: half-steps completed by its last sweep, then
+// kDone once it and every earlier group finished.
+// ---------------------------------------------------------------------------
 template <typename T, int TWM, int NTL>
 __global__ __launch_bounds__(max_threads<TWM>()) void bb_stage(StageArgs a) {
     using C = typename Compute<T>::type;
-    constexpr int LDC = TWM + 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    C* corners = reinterpret_cast<C*>(smem_raw);  // G blocks of LDC*LDC
+    C* corners = reinterpret_cast<C*>(smem_raw);  // G blocks of (TWM+1)^2
     __shared__ int s_group;
     __shared__ int s_ok;
-
-    const int tid = threadIdx.x;
     const int G = blockDim.x / NTL;
-    const int g = tid / NTL;       // lane of this thread
-    const int ltid = tid - g * NTL;
-    C* corner = corners + g * (LDC * LDC);
-    T* __restrict__ A = reinterpret_cast<T*>(a.W) + a.uo;
-    const int64_t S = a.S;
-    const int S32 = (int)a.S;
-    const int n = a.n, b = a.b, tw = a.tw, c = a.c, H = a.H;
     const int ngroups = (a.nsweeps + G - 1) / G;
-
     for (;;) {
-        if (tid == 0) {
+        if (threadIdx.x == 0) {
             int q = atomicAdd(a.claim, 1);
             if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) q = ngroups;
             s_group = q;
@@ -361,121 +489,150 @@ __global__ __launch_bounds__(max_threads<TWM>()) void bb_stage(StageArgs a) {
         __syncthreads();
         const int q = s_group;
         if (q >= ngroups) return;
-        const int r0 = q * G;
-        const int nl = min(G, a.nsweeps - r0);  // lanes holding a sweep
-        const int r = r0 + g;
-        const bool has_sweep = g < nl;
-        const int len = has_sweep ? sweep_halfsteps(n, b, c, r) : 0;
-        const int* prev = r0 > 0 ? a.progress + (r0 - 1) : nullptr;
-        int* last = a.progress + (r0 + nl - 1);
-        // phases until every lane finished: lane 0 is the longest-lived (lengths never grow with r)
-        int P_end = 0;
-        for (int l = 0; l < nl; ++l) P_end = max(P_end, sweep_halfsteps(n, b, c, r0 + l) + H * l);
-        const int len_prev = prev ? sweep_halfsteps(n, b, c, r0 - 1) : 0;
-        int known = 0;      // thread 0: last progress value seen for the previous group
-        int published = 0;  // thread 0: last progress value published for this group
+        GroupArgs ga;
+        ga.A = reinterpret_cast<T*>(a.W) + a.uo;
+        ga.S = a.S;
+        ga.n = a.n;
+        ga.b = a.b;
+        ga.tw = a.tw;
+        ga.c = a.c;
+        ga.H = a.H;
+        ga.nsweeps = a.nsweeps;
+        ga.r0 = q * G;
+        ga.prev = q > 0 ? a.progress + (q - 1) : nullptr;
+        ga.stage_prev = nullptr;
+        ga.last = a.progress + q;
+        ga.abort_flag = a.abort_flag;
+        ga.err_word = a.err_word;
+        ga.spin_limit = a.spin_limit;
+        if (!run_group<T, TWM, NTL>(ga, corners, &s_ok)) return;
+    }
+}
 
-        for (int P = 0; P < P_end; ++P) {
-            // ---- dependency on the previous group (thread 0 polls, then acquires) ----
-            if (tid == 0) {
-                int ok = 1;
-                if (prev) {
-                    int need = 0;
-                    for (int l = 0; l < nl; ++l) {
-                        const int h = P - H * l;
-                        const int ll = sweep_halfsteps(n, b, c, r0 + l);
-                        if (h < 0 || h >= ll) continue;
-                        const int pred_len = l == 0 ? len_prev : sweep_halfsteps(n, b, c, r0 + l - 1);
-                        if (h + H > pred_len) need = kDone;           // predecessor must be DONE
-                        else if (l == 0) need = max(need, h + H);     // lanes > 0 are covered by lock-step
-                    }
-                    if (need > known) {
-                        unsigned spins = 0;
-                        int v;
-                        while ((v = __hip_atomic_load(prev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < need) {
-                            __builtin_amdgcn_s_sleep(1);
-                            if ((++spins & 255u) == 0) {
-                                if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                                    ok = 0;
-                                    break;
-                                }
-                                if (spins > a.spin_limit) {
-                                    __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                                    __hip_atomic_store(a.err_word, 2 /*BB_ERR_TIMEOUT*/, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_SYSTEM);
-                                    ok = 0;
-                                    break;
-                                }
-                            }
-                        }
-                        known = v;
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                    }
-                }
-                s_ok = ok;
-            }
-            __syncthreads();
-            if (!s_ok) return;
-
-            // ---- this phase's half-step of every lane ----
-            const int h = P - H * g;
-            const bool active = has_sweep && h >= 0 && h < len;
-            StepGeom sg{0, 0, 0};
-            double beta_row = 0.0;
-            if (active) {
-                sg = step_geom(n, b, tw, c, r, h >> 1);
-                if ((h & 1) == 0) beta_row = right_task<T, TWM, NTL>(A, S, S32, sg, corner, ltid);
-                else left_task<T, TWM, NTL>(A, S, S32, sg, n, b, corner, ltid);
-            }
-            __builtin_amdgcn_s_waitcnt(0);
-            __syncthreads();  // every wave of every lane has read its row k
-            if (active && (h & 1) == 0 && ltid <= sg.m)
-                A[sg.k + (int64_t)(sg.p + ltid) * S] = static_cast<T>(ltid == 0 ? beta_row : 0.0);
-            __builtin_amdgcn_s_waitcnt(0);
-            __syncthreads();  // phase complete: its stores are visible inside the workgroup
-
-            // ---- publish the progress of this group's last sweep ----
-            if (tid == 0) {
-                const int done_last = min(max(P + 1 - H * (nl - 1), 0),
-                                          sweep_halfsteps(n, b, c, r0 + nl - 1));
-                if (done_last > published) {
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                    __hip_atomic_store(last, done_last, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    published = done_last;
-                }
-            }
-        }
-        // ---- all sweeps of the group finished: DONE once the previous group is DONE ----
-        if (tid == 0) {
-            int ok = 1;
-            if (prev && known < kDone) {
-                unsigned spins = 0;
-                while (__hip_atomic_load(prev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < kDone) {
-                    __builtin_amdgcn_s_sleep(1);
-                    if ((++spins & 255u) == 0) {
-                        if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                            ok = 0;
-                            break;
-                        }
-                        if (spins > a.spin_limit) {
-                            __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            __hip_atomic_store(a.err_word, 2 /*BB_ERR_TIMEOUT*/, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_SYSTEM);
-                            ok = 0;
-                            break;
-                        }
-                    }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            }
-            if (ok) {
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                __hip_atomic_store(last, kDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            s_ok = ok;
+// ---------------------------------------------------------------------------
+// Ragged batch: one persistent launch over every (matrix, stage, group) task of
+// many independent bands.  Tasks are ordered by (stage, group, matrix), so a
+// task's dependencies -- the previous group of its stage, and for group 0 the
+// last group of the previous stage -- always precede it in the claim order.
+// FP16 storage: the workgroup that runs group 0 of a stage first rescales that
+// matrix's working band by a power of two (the stage's scale).
+// ---------------------------------------------------------------------------
+template <typename T, int TWM, int NTL>
+__global__ __launch_bounds__(max_threads<TWM>()) void bb_stage_batched(BatchArgs a) {
+    using C = typename Compute<T>::type;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C* corners = reinterpret_cast<C*>(smem_raw);
+    __shared__ int s_task;
+    __shared__ int s_ok;
+    __shared__ float s_red[32];
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int t = atomicAdd(a.claim, 1);
+            if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) t = a.ntasks;
+            s_task = t;
         }
         __syncthreads();
-        if (!s_ok) return;
+        const int t = s_task;
+        if (t >= a.ntasks) return;
+        const BatchTask tk = a.tasks[t];
+        const BatchMatrix& M = a.mats[tk.matrix];
+        const BatchStage& St = a.stages[M.stage_off + tk.stage];
+        GroupArgs ga;
+        ga.A = reinterpret_cast<T*>(M.W) + M.uo;
+        ga.S = M.S;
+        ga.n = M.n;
+        ga.b = St.b;
+        ga.tw = St.tw;
+        ga.c = St.c;
+        ga.H = St.H;
+        ga.nsweeps = St.nsweeps;
+        ga.r0 = tk.group * (int)(blockDim.x / NTL);
+        ga.prev = tk.group > 0 ? a.progress + St.prog_off + tk.group - 1 : nullptr;
+        ga.stage_prev = nullptr;
+        if (tk.group == 0 && tk.stage > 0) {
+            const BatchStage& Sp = a.stages[M.stage_off + tk.stage - 1];
+            ga.stage_prev = a.progress + Sp.prog_off + Sp.ngroups - 1;
+        }
+        ga.last = a.progress + St.prog_off + tk.group;
+        ga.abort_flag = a.abort_flag;
+        ga.err_word = a.err_word;
+        ga.spin_limit = a.spin_limit;
+        if constexpr (std::is_same<T, _Float16>::value) {
+            if (tk.group == 0) {
+                // the previous stage must be complete before the band is rescaled
+                if (threadIdx.x == 0) {
+                    int ok = 1;
+                    if (ga.stage_prev && poll_ge(ga.stage_prev, kDone, a.abort_flag, a.err_word, a.spin_limit) < 0) ok = 0;
+                    s_ok = ok;
+                }
+                __syncthreads();
+                if (!s_ok) return;
+                ga.stage_prev = nullptr;
+                _Float16* W = reinterpret_cast<_Float16*>(M.W);
+                const int64_t count = (int64_t)M.n * (M.S + 1);
+                float mx = 0.f;
+                for (int64_t i = threadIdx.x; i < count; i += blockDim.x) mx = fmaxf(mx, fabsf(static_cast<float>(W[i])));
+                for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+                if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = mx;
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    float m2 = 0.f;
+                    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m2 = fmaxf(m2, s_red[w]);
+                    const int e_old = a.exps[M.exp_off + tk.stage];
+                    int e_new = e_old;
+                    if (m2 > 0.f && isfinite(m2)) e_new = e_old + (kF16Top - ilogbf(m2));
+                    a.exps[M.exp_off + tk.stage + 1] = e_new;
+                    s_red[0] = __int_as_float(e_new - e_old);
+                }
+                __syncthreads();
+                const int de = __float_as_int(s_red[0]);
+                if (de != 0)
+                    for (int64_t i = threadIdx.x; i < count; i += blockDim.x)
+                        W[i] = static_cast<_Float16>(ldexpf(static_cast<float>(W[i]), de));
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+            }
+        }
+        if (!run_group<T, TWM, NTL>(ga, corners, &s_ok)) return;
+    }
+}
+
+// pack / extract for a batch: the y dimension of the grid strides over the matrices
+template <typename T>
+__global__ void bb_pack_batched(const BatchMatrix* __restrict__ mats, int count, const void* const* __restrict__ bands,
+                                const int64_t* __restrict__ ldbands) {
+    for (int mi = blockIdx.y; mi < count; mi += gridDim.y) {
+        const BatchMatrix& M = mats[mi];
+        const T* band = static_cast<const T*>(bands[mi]);
+        const int64_t ldband = ldbands[mi];
+        T* W = static_cast<T*>(M.W);
+        const int64_t ldw = M.S + 1, total = (int64_t)M.n * ldw;
+        for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+             idx += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t q = idx / ldw, o = idx - q * ldw;
+            const int64_t i = q - M.uo + o;
+            T v = T(0);
+            if (i >= 0 && i <= q && q - i <= M.b) v = band[(M.b_in + i - q) + q * ldband];
+            W[idx] = v;
+        }
+    }
+}
+
+template <typename T>
+__global__ void bb_extract_batched(const BatchMatrix* __restrict__ mats, int count, const int* __restrict__ exps,
+                                   double* const* __restrict__ ds, double* const* __restrict__ es) {
+    for (int mi = blockIdx.y; mi < count; mi += gridDim.y) {
+        const BatchMatrix& M = mats[mi];
+        const T* A = static_cast<const T*>(M.W) + M.uo;
+        const int64_t S = M.S;
+        const int ex = exps ? exps[M.exp_off + M.nstages] : 0;
+        double* d = ds[mi];
+        double* e = es[mi];
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < M.n;
+             i += (int64_t)gridDim.x * blockDim.x) {
+            d[i] = ldexp(static_cast<double>(A[i + i * S]), -ex);
+            if (i + 1 < M.n) e[i] = ldexp(static_cast<double>(A[i + (i + 1) * S]), -ex);
+        }
     }
 }
 
@@ -572,6 +729,79 @@ static hipError_t launch_stage_tw(const StageArgs& a, int twm, int ntl, int lane
         case 16: return launch_stage_nt<T, 16>(a, ntl, lanes, grid, st);
         case 32: return launch_stage_nt<T, 32>(a, ntl, lanes, grid, st);
         default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, int TWM, int NTL>
+static hipError_t launch_batched_t(const BatchArgs& a, int lanes, int grid, hipStream_t st) {
+    using C = typename Compute<T>::type;
+    const size_t smem = (size_t)lanes * (TWM + 1) * (TWM + 1) * sizeof(C);
+    hipLaunchKernelGGL((bb_stage_batched<T, TWM, NTL>), dim3(grid), dim3(NTL * lanes), smem, st, a);
+    return hipGetLastError();
+}
+
+template <typename T, int TWM>
+static hipError_t launch_batched_nt(const BatchArgs& a, int ntl, int lanes, int grid, hipStream_t st) {
+    switch (ntl) {
+        case 64: return launch_batched_t<T, TWM, 64>(a, lanes, grid, st);
+        case 128: return launch_batched_t<T, TWM, 128>(a, lanes, grid, st);
+        case 256: return launch_batched_t<T, TWM, 256>(a, lanes, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+static hipError_t launch_batched_tw(const BatchArgs& a, int twm, int ntl, int lanes, int grid, hipStream_t st) {
+    switch (twm) {
+        case 8: return launch_batched_nt<T, 8>(a, ntl, lanes, grid, st);
+        case 16: return launch_batched_nt<T, 16>(a, ntl, lanes, grid, st);
+        case 32: return launch_batched_nt<T, 32>(a, ntl, lanes, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batched(int dtype, const BatchArgs& a, int twm, int ntl, int lanes, int grid, hipStream_t st) {
+    if (lanes < 1 || ntl * lanes > stage_max_threads(twm)) return hipErrorInvalidValue;
+    switch (dtype) {
+        case 0: return launch_batched_tw<double>(a, twm, ntl, lanes, grid, st);
+        case 1: return launch_batched_tw<float>(a, twm, ntl, lanes, grid, st);
+        default: return launch_batched_tw<_Float16>(a, twm, ntl, lanes, grid, st);
+    }
+}
+
+template <typename T>
+static hipError_t launch_pack_batched_t(const BatchMatrix* mats, int count, int64_t max_elems, const void* const* bands,
+                                        const int64_t* ldbands, hipStream_t st) {
+    const int gx = (int)std::max<int64_t>(1, std::min<int64_t>((max_elems + 255) / 256, 1024));
+    const int gy = std::min(count, 65535);
+    hipLaunchKernelGGL(bb_pack_batched<T>, dim3(gx, gy), dim3(256), 0, st, mats, count, bands, ldbands);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_batched(int dtype, const BatchMatrix* mats, int count, int64_t max_elems,
+                               const void* const* bands, const int64_t* ldbands, hipStream_t st) {
+    switch (dtype) {
+        case 0: return launch_pack_batched_t<double>(mats, count, max_elems, bands, ldbands, st);
+        case 1: return launch_pack_batched_t<float>(mats, count, max_elems, bands, ldbands, st);
+        default: return launch_pack_batched_t<_Float16>(mats, count, max_elems, bands, ldbands, st);
+    }
+}
+
+template <typename T>
+static hipError_t launch_extract_batched_t(const BatchMatrix* mats, int count, int64_t max_n, const int* exps,
+                                           double* const* ds, double* const* es, hipStream_t st) {
+    const int gx = (int)std::max<int64_t>(1, std::min<int64_t>((max_n + 255) / 256, 1024));
+    const int gy = std::min(count, 65535);
+    hipLaunchKernelGGL(bb_extract_batched<T>, dim3(gx, gy), dim3(256), 0, st, mats, count, exps, ds, es);
+    return hipGetLastError();
+}
+
+hipError_t launch_extract_batched(int dtype, const BatchMatrix* mats, int count, int64_t max_n, const int* exps,
+                                  double* const* ds, double* const* es, hipStream_t st) {
+    switch (dtype) {
+        case 0: return launch_extract_batched_t<double>(mats, count, max_n, exps, ds, es, st);
+        case 1: return launch_extract_batched_t<float>(mats, count, max_n, exps, ds, es, st);
+        default: return launch_extract_batched_t<_Float16>(mats, count, max_n, exps, ds, es, st);
     }
 }
 

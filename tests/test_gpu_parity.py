@@ -264,3 +264,83 @@ def test_c3_fp64_properties_at_full_size(bb):
     assert d[0] == band[0, b]
     row0 = np.array([band[j, b - j] for j in range(1, b + 1)])
     assert abs(abs(e[0]) - np.linalg.norm(row0)) <= 8 * EPS64 * np.linalg.norm(row0)
+
+
+# ------------------------------------------------------------------ ragged batch
+def _batch_case(count, seed, n_lo, n_hi, bands):
+    return inputs.ragged_batch(count=count, seed=seed, n_lo=n_lo, n_hi=n_hi, bands=bands)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_batched_equals_individual_calls_bitwise(bb, dtype):
+    """One persistent launch over a ragged batch computes exactly what one
+    bb_reduce per matrix computes (same per-task arithmetic, same order)."""
+    _say("case ragged batch of 24, %s" % dtype)
+    mats = _batch_case(24, 7, 40, 700, (3, 16, 33))
+    mats.append((1, 4, np.array([[0.0, 0.0, 0.0, 0.0, 1.5]])))   # n = 1
+    mats.append((2, 1, np.array([[0.0, 1.0], [2.0, 3.0]])))      # bidiagonal already
+    bb.reset_params()
+    bb.set_params(tw=16 if dtype == torch.float64 else 32)
+    bands = [torch.from_numpy(np.ascontiguousarray(bd)).cuda().to(dtype) for (_, _, bd) in mats]
+    ns = [m[0] for m in mats]
+    bs = [m[1] for m in mats]
+    ds, es = bb.bb_reduce_batched(bands, ns, bs)
+    assert bb.stream_status() == 0
+    for t, n, b, dd, ee in zip(bands, ns, bs, ds, es):
+        d1, e1 = bb.bb_reduce(t, n, b)
+        assert np.array_equal(dd.cpu().numpy(), d1.cpu().numpy())
+        assert np.array_equal(ee.cpu().numpy(), e1.cpu().numpy())
+    # FP64: also the oracle, bitwise
+    if dtype == torch.float64:
+        for (n, b, bd), dd, ee in list(zip(mats, ds, es))[:6]:
+            do, eo = oracle.reduce(bd, n, b, 16)
+            assert np.array_equal(dd.cpu().numpy(), do) and np.array_equal(ee.cpu().numpy(), eo)
+    bb.reset_params()
+
+
+def test_batched_fp16_matches_individual_calls(bb):
+    mats = _batch_case(12, 9, 64, 400, (16, 32))
+    bb.reset_params()
+    bands = [torch.from_numpy(bd).cuda().to(torch.float16) for (_, _, bd) in mats]
+    ns = [m[0] for m in mats]
+    bs = [m[1] for m in mats]
+    ds, es = bb.bb_reduce_batched(bands, ns, bs)
+    for t, n, b, dd, ee in zip(bands, ns, bs, ds, es):
+        d1, e1 = bb.bb_reduce(t, n, b)
+        assert np.array_equal(dd.cpu().numpy(), d1.cpu().numpy())
+        assert np.array_equal(ee.cpu().numpy(), e1.cpu().numpy())
+
+
+def test_batched_graph_capture_replays(bb):
+    """The batched call captured into a hipGraph replays correctly several times,
+    with eager work and synchronisation between the replays."""
+    mats = _batch_case(16, 11, 64, 500, (16, 32, 64))
+    bb.reset_params()
+    bands = [torch.from_numpy(bd).cuda().to(torch.float32) for (_, _, bd) in mats]
+    ns = [m[0] for m in mats]
+    bs = [m[1] for m in mats]
+    ds = [torch.empty(max(n, 1), dtype=torch.float64, device="cuda") for n in ns]
+    es = [torch.empty(max(n - 1, 1), dtype=torch.float64, device="cuda") for n in ns]
+    ref_d, ref_e = bb.bb_reduce_batched(bands, ns, bs, ds=ds, es=es)   # eager call builds the plan
+    ref_d = [x.cpu().numpy().copy() for x in ref_d]
+    ref_e = [x.cpu().numpy().copy() for x in ref_e]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        bb.bb_reduce_batched(bands, ns, bs, ds=ds, es=es, stream=s)     # warm the plan on this stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        bb.bb_reduce_batched(bands, ns, bs, ds=ds, es=es, stream=s)
+    for rep in range(3):
+        for x in ds:
+            x.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for x, rd in zip(ds, ref_d):
+            assert np.array_equal(x[: len(rd)].cpu().numpy(), rd)
+        for x, re_ in zip(es, ref_e):
+            assert np.array_equal(x[: len(re_)].cpu().numpy(), re_)
+        _ = torch.ones(1000, device="cuda").sum().item()   # eager work between replays
