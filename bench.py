@@ -109,6 +109,9 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=6144)
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="before the workload, run one device copy of this many MiB (a known-size kernel "
+                         "against which HBM byte counters are calibrated)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this benchmark runs on exactly one GPU (the reduction of one band is a single-GPU "
@@ -127,6 +130,16 @@ def main():
     band64 = torch.from_numpy(band).to(dev)
     print("[bench] workload n=%d b=%d, steps=%d warmup=%d" % (n, b, args.steps, args.warmup), file=sys.stderr,
           flush=True)
+    if args.copy_calib_mib > 0:
+        nel = args.copy_calib_mib * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] calibration copy: %d MiB read + %d MiB written" % (args.copy_calib_mib, args.copy_calib_mib),
+              file=sys.stderr, flush=True)
+        del src, dst
     bb.reset_params()
     ms64, stage_ms, launches, d, e = time_reductions(bb, torch, band64, n, b, args.steps, args.warmup, "fp64")
     p = bb.autotune(n, b, bb.F64)  # reports the parameters the call used (no tuning run when cached)

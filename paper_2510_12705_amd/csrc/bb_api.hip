@@ -21,6 +21,7 @@ namespace {
 struct DeviceState {
     bool init = false;
     int cus = 0;
+    size_t lds_per_block = 65536;  // largest dynamic LDS allocation of one workgroup
     int* err_host = nullptr;  // host-mapped error word
     int* err_dev = nullptr;
 };
@@ -54,6 +55,7 @@ int device_state(DeviceState** out) {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return BB_ERR_NODEVICE;
         s.cus = prop.multiProcessorCount;
+        if (prop.sharedMemPerBlock > 0) s.lds_per_block = prop.sharedMemPerBlock;
         if (hipHostMalloc((void**)&s.err_host, sizeof(int), hipHostMallocMapped | hipHostMallocCoherent) !=
             hipSuccess)
             return BB_ERR_NOMEM;
@@ -79,7 +81,7 @@ struct Launch {
     int tw, ntl, lanes, groups_per_cu, lag;
 };
 
-Launch resolve(int64_t n, int64_t b, int dtype) {
+Launch resolve(int64_t n, int64_t b, int dtype, size_t lds_limit = 65536) {
     bb_params_t p;
     {
         std::lock_guard<std::mutex> lk(g_mu);
@@ -94,10 +96,10 @@ Launch resolve(int64_t n, int64_t b, int dtype) {
     L.lanes = p.sweeps_per_group ? p.sweeps_per_group : cached ? t.lanes : bbp::default_lanes(L.ntl);
     L.groups_per_cu = p.groups_per_cu ? p.groups_per_cu : cached ? t.groups_per_cu : 2;
     L.lag = p.lag;
-    // keep the per-workgroup LDS corner blocks within 64 KB
-    const size_t per_lane = (size_t)(bbp::kernel_twm(L.tw) + 1) * (bbp::kernel_twm(L.tw) + 1) * elem_size_c(dtype);
-    while (L.lanes > 1 && (size_t)L.lanes * per_lane > 65536) --L.lanes;
-    while (L.lanes > 1 && L.lanes * L.ntl > bbk::stage_max_threads(bbp::kernel_twm(L.tw))) --L.lanes;
+    // fit the workgroup's LDS (corners + staging blocks) and thread limits
+    const int twm = bbp::kernel_twm(L.tw);
+    while (L.lanes > 1 && bbk::stage_lds_bytes(dtype, twm, L.ntl, L.lanes) > lds_limit) --L.lanes;
+    while (L.lanes > 1 && L.lanes * L.ntl > bbk::stage_max_threads(twm)) --L.lanes;
     return L;
 }
 
@@ -356,7 +358,7 @@ int bb_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, int64_t 
 
     const int64_t b_in = b;
     const int64_t bb = std::min<int64_t>(b, n - 1);
-    Launch L = resolve(n, bb, dtype);
+    Launch L = resolve(n, bb, dtype, ds->lds_per_block);
     if (L.tw < 1 || L.tw > bbp::kMaxTW) return BB_ERR_UNSUPPORTED;
     bbp::Plan plan = bbp::make_plan(bb, L.tw);
     Workspace ws = workspace_layout(n, bb, dtype, L.tw);
@@ -449,7 +451,7 @@ int bb_reduce_batched(int64_t count, const int64_t* n, const int64_t* b, bb_dtyp
         max_n = std::max(max_n, n[i]);
         max_b = std::max(max_b, std::min(b[i], std::max<int64_t>(n[i] - 1, 0)));
     }
-    Launch L = resolve(max_n, max_b, dtype);
+    Launch L = resolve(max_n, max_b, dtype, ds->lds_per_block);
     if (L.tw < 1 || L.tw > bbp::kMaxTW) return BB_ERR_UNSUPPORTED;
     BatchPlan* bp = nullptr;
     rc = batch_plan(count, n, b, dtype, L, st, &bp);
@@ -573,7 +575,9 @@ extern "C" int bb_autotune(int64_t n, int64_t b, bb_dtype_t dtype, void* stream,
     if (n < 0) return -1;
     if (b < 0) return -2;
     if (dtype != BB_F64 && dtype != BB_F32 && dtype != BB_F16) return -3;
-    Launch L = resolve(n, std::min<int64_t>(b, std::max<int64_t>(n - 1, 0)), dtype);
+    DeviceState* ds = nullptr;
+    const size_t lds = device_state(&ds) == BB_OK ? ds->lds_per_block : 65536;
+    Launch L = resolve(n, std::min<int64_t>(b, std::max<int64_t>(n - 1, 0)), dtype, lds);
     if (out) *out = bb_params_t{L.tw, L.ntl, L.lanes, L.groups_per_cu, L.lag};
     return BB_OK;
 }

@@ -69,6 +69,8 @@ hipError_t launch_extract_f16(const void* W, int64_t n, int64_t ldw, int64_t uo,
                               double* d, double* e, hipStream_t st);
 // largest workgroup (ntl * lanes) the stage kernel variant for tilewidth bound twm accepts
 int stage_max_threads(int twm);
+// dynamic LDS bytes of one stage workgroup (lanes corners + per-wave staging blocks)
+size_t stage_lds_bytes(int dtype, int twm, int ntl, int lanes);
 // one stage: `lanes` consecutive sweeps per workgroup, `ntl` threads per lane
 hipError_t launch_stage(int dtype, const StageArgs& a, int twm, int ntl, int lanes, int grid, hipStream_t st);
 

@@ -134,6 +134,31 @@ __global__ void bb_fill_i32(int* __restrict__ p, int64_t count, int value) {
 }
 
 // ---------------------------------------------------------------------------
+// Addressing.  A lane's window base is the same for every thread of a wave (a
+// wave never spans two lanes), so it is moved to scalar registers and every
+// access becomes scalar base + 32-bit unsigned byte offset (one VGPR per address).
+// ---------------------------------------------------------------------------
+template <typename P>
+__device__ __forceinline__ P* wave_uniform(P* ptr) {
+    const uint64_t v = reinterpret_cast<uint64_t>(ptr);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+    return reinterpret_cast<P*>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+template <typename T>
+__device__ __forceinline__ T& at(T* base, int off) {
+    return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + static_cast<uint32_t>(off) * sizeof(T));
+}
+
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
+
+// one dword per thread from global memory straight into LDS at lds + 4 * lane
+__device__ __forceinline__ void dma_dword(const uint32_t* g, uint32_t* lds) {
+    __builtin_amdgcn_global_load_lds(g, (lds_void_ptr)(lds), 4, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
 // Householder application to one row / column segment of m+1 values held in
 // registers: a <- a - (tau (a . v)) v.
 //   FP64 storage: the dot is summed left to right with separate multiply and add
@@ -176,10 +201,10 @@ __device__ __forceinline__ void apply_segment(C (&av)[TWM + 1], const C (&vs)[TW
 // `base` points at A(k, p) of the current step; in-window offsets fit in 32 bits.
 template <typename T, typename C, int TWM>
 __device__ __forceinline__ void load_row(C (&av)[TWM + 1], const T* __restrict__ base, int S, int di, int m) {
-    const T* row = base + di;  // A(k + di, p + t) = row[t * S]
+    // A(k + di, p + t) = base[di + t * S]
 #pragma unroll
     for (int t = 0; t <= TWM; ++t) {
-        const C v = to_c(row[min(t, m) * S]);
+        const C v = to_c(at(const_cast<T*>(base), di + min(t, m) * S));
         av[t] = t <= m ? v : C(0);
     }
 }
@@ -189,9 +214,8 @@ __device__ __forceinline__ void load_row(C (&av)[TWM + 1], const T* __restrict__
 // (stores of one thread to one address keep program order).
 template <typename T, typename C, int TWM>
 __device__ __forceinline__ void store_row(const C (&av)[TWM + 1], T* __restrict__ base, int S, int di, int m) {
-    T* row = base + di;
 #pragma unroll
-    for (int t = TWM; t >= 0; --t) row[min(t, m) * S] = static_cast<T>(av[t]);
+    for (int t = TWM; t >= 0; --t) at(base, di + min(t, m) * S) = static_cast<T>(av[t]);
 }
 
 // column q = p + 1 + ci of rows p..p+m; columns p+1..p+m come from the LDS corner
@@ -271,8 +295,8 @@ __device__ __forceinline__ double right_task(T* __restrict__ A, int64_t S, int S
     const int k = g.k, p = g.p, m = g.m;
     const int lane = ltid & (kWave - 1);
     const int rows = p + m - k;  // rows k+1 .. p+m
-    T* base = A + k + (int64_t)p * S;  // A(k, p)
-    const double xl = static_cast<double>(base[min(lane, m) * S32]);
+    T* base = wave_uniform(A + k + (int64_t)p * S);  // A(k, p)
+    const double xl = static_cast<double>(at(base, min(lane, m) * S32));
     int ri = ltid;
     C av[TWM + 1];
     load_row<T, C, TWM>(av, base, S32, 1 + min(ri, rows - 1), m);
@@ -297,32 +321,88 @@ __device__ __forceinline__ double right_task(T* __restrict__ A, int64_t S, int S
 
 // Left task of one lane: reflector from A[p..p+m, p] (held in the corner), applied
 // to rows p..p+m of columns p+1..L; writes column p as (beta, 0, ..., 0).
+// Each wave moves its columns through its own LDS block of kWave columns with a
+// pitch of TWM+1 elements: in global memory a column's m+1 rows are contiguous,
+// so the block is filled and written back as contiguous runs; each thread then
+// updates one column in registers with the same sequential dot as every other
+// segment update.  For 4- and 8-byte storage the block is filled by
+// global-to-LDS loads (no registers); columns p+1..p+m come from the corner.  A
+// wave exchanges data only with itself through its block (no barrier).
 template <typename T, int TWM, int NTL>
 __device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32, StepGeom g, int n, int b,
-                                          const typename Compute<T>::type* corner, int ltid) {
+                                          const typename Compute<T>::type* corner,
+                                          typename Compute<T>::type* stage, int ltid) {
     using C = typename Compute<T>::type;
     constexpr int LDC = TWM + 1;
     const int p = g.p, m = g.m;
     const int lane = ltid & (kWave - 1);
+    const int wv = ltid / kWave;
     const int L = min(p + m + b, n - 1);
-    const int cols = L - p;  // columns p+1 .. L
-    int ci = ltid;
-    T* base = A + p + (int64_t)p * S;  // A(p, p)
-    C av[TWM + 1];
-    load_col<T, C, TWM>(av, base, S32, corner, min(ci, cols - 1), m);
+    const int cols = L - p;  // columns p+1 .. L; column p+1+ci starts at base + (1 + ci) * S
+    T* base = wave_uniform(A + p + (int64_t)p * S);  // A(p, p)
+    C* blk = stage + wv * (kWave * LDC);
     const double xl = static_cast<double>(corner[min(lane, m) * LDC]);
     C vs[TWM + 1];
     double taud, betad;
     house_uniform<TWM>(xl, m, vs, taud, betad);
     const C tau = static_cast<C>(taud);
-    while (ci < cols) {
+    for (int c0 = wv * kWave; c0 < cols; c0 += NTL) {
+        if constexpr (sizeof(T) >= 4) {
+            static_assert(sizeof(T) == sizeof(C), "4/8-byte storage is computed in its own type");
+            constexpr int DW = sizeof(T) / 4;  // dwords per element
+            constexpr int PITCH = LDC * DW;    // dwords per column in the block
+            const uint32_t* gd = reinterpret_cast<const uint32_t*>(base);
+            uint32_t* bd = reinterpret_cast<uint32_t*>(blk);
+#pragma unroll 4
+            for (int u = 0; u < PITCH; ++u) {
+                const int j = u * kWave + lane;
+                const int col = j / PITCH, w = j - col * PITCH;
+                const int ci = c0 + col;
+                if (w < (m + 1) * DW && ci >= m && ci < cols)
+                    dma_dword(reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(gd) +
+                                                                static_cast<uint32_t>(((1 + ci) * S32 * DW + w) * 4)),
+                              bd + u * kWave);
+            }
+            if (c0 + lane < m) {
+#pragma unroll
+                for (int t = 0; t <= TWM; ++t)
+                    if (t <= m) blk[lane * LDC + t] = corner[t * LDC + c0 + lane + 1];
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+        } else {
+#pragma unroll
+            for (int u = 0; u < LDC; ++u) {
+                const int e = u * kWave + lane;
+                const int col = e / LDC, t = e - col * LDC;
+                const int ci = c0 + col;
+                C v = C(0);
+                if (t <= m && ci < cols) v = ci < m ? corner[t * LDC + ci + 1] : to_c(at(base, (1 + ci) * S32 + t));
+                blk[e] = v;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        C av[TWM + 1];
+#pragma unroll
+        for (int t = 0; t <= TWM; ++t) av[t] = t <= m ? blk[lane * LDC + t] : C(0);
         if (taud != 0.0) apply_segment<C, TWM>(av, vs, tau, m);
-        store_col<T, C, TWM>(av, base, S32, ci, m);
-        ci += NTL;
-        if (ci < cols) load_col<T, C, TWM>(av, base, S32, corner, ci, m);
+#pragma unroll
+        for (int t = 0; t <= TWM; ++t) blk[lane * LDC + t] = av[t];
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll 4
+        for (int u = 0; u < LDC; ++u) {
+            const int e = u * kWave + lane;
+            const int col = e / LDC, t = e - col * LDC;
+            const int ci = c0 + col;
+            if (t <= m && ci < cols) at(base, (1 + ci) * S32 + t) = static_cast<T>(blk[e]);
+        }
+        __builtin_amdgcn_wave_barrier();
     }
-    if (ltid <= m) base[ltid] = static_cast<T>(ltid == 0 ? betad : 0.0);
+    if (ltid <= m) at(base, ltid) = static_cast<T>(ltid == 0 ? betad : 0.0);
 }
+
+// LDS of one lane: its (TWM+1)^2 corner, then one staging block per wave
+template <int TWM, int NTL>
+constexpr int lane_lds_elems() { return (TWM + 1) * (TWM + 1) + NTL * (TWM + 1); }
 
 // largest workgroup a variant is compiled for (wider windows need more registers)
 template <int TWM>
@@ -376,6 +456,7 @@ __device__ bool run_group(const GroupArgs& ga, typename Compute<T>::type* corner
     const int g = tid / NTL;
     const int ltid = tid - g * NTL;
     C* corner = corners + g * (LDC * LDC);
+    C* stage = corners + G * (LDC * LDC) + g * (NTL * LDC);
     T* __restrict__ A = reinterpret_cast<T*>(ga.A);
     const int64_t S = ga.S;
     const int S32 = (int)ga.S;
@@ -430,7 +511,7 @@ __device__ bool run_group(const GroupArgs& ga, typename Compute<T>::type* corner
         if (active) {
             sg = step_geom(n, b, tw, c, r, h >> 1);
             if ((h & 1) == 0) beta_row = right_task<T, TWM, NTL>(A, S, S32, sg, corner, ltid);
-            else left_task<T, TWM, NTL>(A, S, S32, sg, n, b, corner, ltid);
+            else left_task<T, TWM, NTL>(A, S, S32, sg, n, b, corner, stage, ltid);
         }
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();  // every wave of every lane has read its row k
@@ -707,7 +788,7 @@ hipError_t launch_fill(int* p, int64_t count, int value, hipStream_t st) {
 template <typename T, int TWM, int NTL>
 static hipError_t launch_stage_t(const StageArgs& a, int lanes, int grid, hipStream_t st) {
     using C = typename Compute<T>::type;
-    const size_t smem = (size_t)lanes * (TWM + 1) * (TWM + 1) * sizeof(C);
+    const size_t smem = (size_t)lanes * lane_lds_elems<TWM, NTL>() * sizeof(C);
     hipLaunchKernelGGL((bb_stage<T, TWM, NTL>), dim3(grid), dim3(NTL * lanes), smem, st, a);
     return hipGetLastError();
 }
@@ -735,7 +816,7 @@ static hipError_t launch_stage_tw(const StageArgs& a, int twm, int ntl, int lane
 template <typename T, int TWM, int NTL>
 static hipError_t launch_batched_t(const BatchArgs& a, int lanes, int grid, hipStream_t st) {
     using C = typename Compute<T>::type;
-    const size_t smem = (size_t)lanes * (TWM + 1) * (TWM + 1) * sizeof(C);
+    const size_t smem = (size_t)lanes * lane_lds_elems<TWM, NTL>() * sizeof(C);
     hipLaunchKernelGGL((bb_stage_batched<T, TWM, NTL>), dim3(grid), dim3(NTL * lanes), smem, st, a);
     return hipGetLastError();
 }
@@ -806,6 +887,11 @@ hipError_t launch_extract_batched(int dtype, const BatchMatrix* mats, int count,
 }
 
 int stage_max_threads(int twm) { return twm >= 16 ? max_threads<16>() : max_threads<8>(); }
+
+size_t stage_lds_bytes(int dtype, int twm, int ntl, int lanes) {
+    const size_t c = dtype == 0 ? sizeof(double) : sizeof(float);
+    return (size_t)lanes * ((size_t)(twm + 1) * (twm + 1) + (size_t)ntl * (twm + 1)) * c;
+}
 
 hipError_t launch_stage(int dtype, const StageArgs& a, int twm, int ntl, int lanes, int grid, hipStream_t st) {
     if (lanes < 1 || ntl * lanes > stage_max_threads(twm)) return hipErrorInvalidValue;
