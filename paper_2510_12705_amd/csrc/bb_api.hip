@@ -77,8 +77,13 @@ size_t elem_size_c(int dtype) { return dtype == BB_F64 ? 8 : 4; }  // compute ty
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Launch shape.  ntl / lanes are those of the first stage; unless fixed by the
+// caller (or an autotuned entry) they are re-derived for every stage from its
+// window height (stage_shape).
 struct Launch {
     int tw, ntl, lanes, groups_per_cu, lag;
+    bool ntl_fixed, lanes_fixed;
+    size_t lds_limit;
 };
 
 Launch resolve(int64_t n, int64_t b, int dtype, size_t lds_limit = 65536) {
@@ -92,8 +97,11 @@ Launch resolve(int64_t n, int64_t b, int dtype, size_t lds_limit = 65536) {
     Launch L;
     L.tw = p.tw ? p.tw : cached ? t.tw : bbp::default_tw(dtype);
     int rows = (int)std::min<int64_t>(b, std::max<int64_t>(n - 1, 1)) + L.tw;
-    L.ntl = p.threads_per_window ? p.threads_per_window : cached ? t.ntl : bbp::default_threads(rows);
-    L.lanes = p.sweeps_per_group ? p.sweeps_per_group : cached ? t.lanes : bbp::default_lanes(L.ntl);
+    L.ntl = p.threads_per_window ? p.threads_per_window : cached ? t.ntl : bbp::default_threads(rows, dtype);
+    L.lanes = p.sweeps_per_group ? p.sweeps_per_group : cached ? t.lanes : bbp::default_lanes(L.ntl, dtype);
+    L.ntl_fixed = p.threads_per_window != 0 || cached;
+    L.lanes_fixed = p.sweeps_per_group != 0 || cached;
+    L.lds_limit = lds_limit;
     L.groups_per_cu = p.groups_per_cu ? p.groups_per_cu : cached ? t.groups_per_cu : 2;
     L.lag = p.lag;
     // fit the workgroup's LDS (corners + staging blocks) and thread limits
@@ -101,6 +109,17 @@ Launch resolve(int64_t n, int64_t b, int dtype, size_t lds_limit = 65536) {
     while (L.lanes > 1 && bbk::stage_lds_bytes(dtype, twm, L.ntl, L.lanes) > lds_limit) --L.lanes;
     while (L.lanes > 1 && L.lanes * L.ntl > bbk::stage_max_threads(twm)) --L.lanes;
     return L;
+}
+
+// threads per window and sweeps per workgroup for one stage
+void stage_shape(const Launch& L, const bbp::Stage& sg, int dtype, int* ntl, int* lanes) {
+    const int twm = bbp::kernel_twm(sg.tw);
+    int nt = L.ntl_fixed ? L.ntl : bbp::default_threads(sg.b + sg.tw, dtype);
+    int ln = L.lanes_fixed ? L.lanes : bbp::default_lanes(nt, dtype);
+    while (ln > 1 && bbk::stage_lds_bytes(dtype, twm, nt, ln) > L.lds_limit) --ln;
+    while (ln > 1 && ln * nt > bbk::stage_max_threads(twm)) --ln;
+    *ntl = nt;
+    *lanes = ln;
 }
 
 struct Workspace {
@@ -397,7 +416,9 @@ int bb_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, int64_t 
             rc = check_hip(bbk::launch_f16_rescale(W, n * ws.ldw, f16_amax + s, f16_exps, s, st));
         if (rc) break;
         const int twm = bbp::kernel_twm(sg.tw);
-        const int64_t ngroups = (a.nsweeps + L.lanes - 1) / L.lanes;
+        int ntl_s = 0, lanes_s = 0;
+        stage_shape(L, sg, dtype, &ntl_s, &lanes_s);
+        const int64_t ngroups = (a.nsweeps + lanes_s - 1) / lanes_s;
         const int grid = (int)std::min<int64_t>(ngroups, (int64_t)ds->cus * L.groups_per_cu);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         bool timed = false;
@@ -407,7 +428,7 @@ int bb_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, int64_t 
         }
         if (timed && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess)
             hipEventRecord(e0, st);
-        rc = check_hip(bbk::launch_stage(dtype, a, twm, L.ntl, L.lanes, grid, st));
+        rc = check_hip(bbk::launch_stage(dtype, a, twm, ntl_s, lanes_s, grid, st));
         if (timed && e1) {
             hipEventRecord(e1, st);
             std::lock_guard<std::mutex> lk(g_mu);

@@ -328,6 +328,57 @@ __device__ __forceinline__ double right_task(T* __restrict__ A, int64_t S, int S
 // segment update.  For 4- and 8-byte storage the block is filled by
 // global-to-LDS loads (no registers); columns p+1..p+m come from the corner.  A
 // wave exchanges data only with itself through its block (no barrier).
+// Fill a wave's LDS block with columns c0 .. c0+63 (those < cols) of the left
+// task's window; columns below m come from the corner.  4/8-byte storage: the
+// loads go straight to LDS and complete at the next s_waitcnt vmcnt.
+template <typename T, int TWM>
+__device__ __forceinline__ void left_stage_in(const T* __restrict__ base, int S32, const typename Compute<T>::type* corner,
+                                              typename Compute<T>::type* blk, int c0, int m, int cols, int lane) {
+    using C = typename Compute<T>::type;
+    constexpr int LDC = TWM + 1;
+    if constexpr (sizeof(T) >= 4) {
+        static_assert(sizeof(T) == sizeof(C), "4/8-byte storage is computed in its own type");
+        constexpr int DW = sizeof(T) / 4;  // dwords per element
+        constexpr int PITCH = LDC * DW;    // dwords per column in the block
+        const uint32_t* gd = reinterpret_cast<const uint32_t*>(base);
+        uint32_t* bd = reinterpret_cast<uint32_t*>(blk);
+#pragma unroll 4
+        for (int u = 0; u < PITCH; ++u) {
+            const int j = u * kWave + lane;
+            const int col = j / PITCH, w = j - col * PITCH;
+            const int ci = c0 + col;
+            if (w < (m + 1) * DW && ci >= m && ci < cols)
+                dma_dword(reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(gd) +
+                                                            static_cast<uint32_t>(((1 + ci) * S32 * DW + w) * 4)),
+                          bd + u * kWave);
+        }
+        if (c0 + lane < m) {
+#pragma unroll
+            for (int t = 0; t <= TWM; ++t)
+                if (t <= m) blk[lane * LDC + t] = corner[t * LDC + c0 + lane + 1];
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < LDC; ++u) {
+            const int e = u * kWave + lane;
+            const int col = e / LDC, t = e - col * LDC;
+            const int ci = c0 + col;
+            C v = C(0);
+            if (t <= m && ci < cols) v = ci < m ? corner[t * LDC + ci + 1] : to_c(at(const_cast<T*>(base), (1 + ci) * S32 + t));
+            blk[e] = v;
+        }
+    }
+}
+
+// Left task of one lane: reflector from A[p..p+m, p] (held in the corner), applied
+// to rows p..p+m of columns p+1..L; writes column p as (beta, 0, ..., 0).
+// Each wave moves its columns through its own LDS block of kWave columns with a
+// pitch of TWM+1 elements: in global memory a column's m+1 rows are contiguous,
+// so the block is filled and written back as contiguous runs; each thread then
+// updates one column in registers with the same sequential dot as every other
+// segment update.  The first block's loads are in flight while the reflector is
+// generated.  A wave exchanges data only with itself through its block (no
+// barrier).
 template <typename T, int TWM, int NTL>
 __device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32, StepGeom g, int n, int b,
                                           const typename Compute<T>::type* corner,
@@ -342,44 +393,15 @@ __device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32,
     T* base = wave_uniform(A + p + (int64_t)p * S);  // A(p, p)
     C* blk = stage + wv * (kWave * LDC);
     const double xl = static_cast<double>(corner[min(lane, m) * LDC]);
+    const int c_first = wv * kWave;
+    if (c_first < cols) left_stage_in<T, TWM>(base, S32, corner, blk, c_first, m, cols, lane);
     C vs[TWM + 1];
     double taud, betad;
     house_uniform<TWM>(xl, m, vs, taud, betad);
     const C tau = static_cast<C>(taud);
-    for (int c0 = wv * kWave; c0 < cols; c0 += NTL) {
-        if constexpr (sizeof(T) >= 4) {
-            static_assert(sizeof(T) == sizeof(C), "4/8-byte storage is computed in its own type");
-            constexpr int DW = sizeof(T) / 4;  // dwords per element
-            constexpr int PITCH = LDC * DW;    // dwords per column in the block
-            const uint32_t* gd = reinterpret_cast<const uint32_t*>(base);
-            uint32_t* bd = reinterpret_cast<uint32_t*>(blk);
-#pragma unroll 4
-            for (int u = 0; u < PITCH; ++u) {
-                const int j = u * kWave + lane;
-                const int col = j / PITCH, w = j - col * PITCH;
-                const int ci = c0 + col;
-                if (w < (m + 1) * DW && ci >= m && ci < cols)
-                    dma_dword(reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(gd) +
-                                                                static_cast<uint32_t>(((1 + ci) * S32 * DW + w) * 4)),
-                              bd + u * kWave);
-            }
-            if (c0 + lane < m) {
-#pragma unroll
-                for (int t = 0; t <= TWM; ++t)
-                    if (t <= m) blk[lane * LDC + t] = corner[t * LDC + c0 + lane + 1];
-            }
-            __builtin_amdgcn_s_waitcnt(0);
-        } else {
-#pragma unroll
-            for (int u = 0; u < LDC; ++u) {
-                const int e = u * kWave + lane;
-                const int col = e / LDC, t = e - col * LDC;
-                const int ci = c0 + col;
-                C v = C(0);
-                if (t <= m && ci < cols) v = ci < m ? corner[t * LDC + ci + 1] : to_c(at(base, (1 + ci) * S32 + t));
-                blk[e] = v;
-            }
-        }
+    for (int c0 = c_first; c0 < cols; c0 += NTL) {
+        if (c0 != c_first) left_stage_in<T, TWM>(base, S32, corner, blk, c0, m, cols, lane);
+        __builtin_amdgcn_s_waitcnt(0);
         __builtin_amdgcn_wave_barrier();
         C av[TWM + 1];
 #pragma unroll
@@ -482,6 +504,12 @@ __device__ bool run_group(const GroupArgs& ga, typename Compute<T>::type* corner
     }
     // (the first phase's barrier publishes *s_ok)
 
+    // Row k of a right task is rewritten in the lane's next phase (its left task)
+    // when c >= 2: no half-step that the lag rule lets run before that phase ends
+    // touches those entries.  With c = 1 some do, so the row is written after an
+    // extra barrier in the same phase.
+    const bool defer_rowk = c >= 2;
+    double beta_row = 0.0;
     for (int P = 0; P < P_end; ++P) {
         // ---- dependency on the previous group (thread 0 polls, then acquires) ----
         if (tid == 0 && *s_ok && ga.prev) {
@@ -507,16 +535,24 @@ __device__ bool run_group(const GroupArgs& ga, typename Compute<T>::type* corner
         const int h = P - H * g;
         const bool active = has_sweep && h >= 0 && h < len;
         StepGeom sg{0, 0, 0};
-        double beta_row = 0.0;
         if (active) {
             sg = step_geom(n, b, tw, c, r, h >> 1);
-            if ((h & 1) == 0) beta_row = right_task<T, TWM, NTL>(A, S, S32, sg, corner, ltid);
-            else left_task<T, TWM, NTL>(A, S, S32, sg, n, b, corner, stage, ltid);
+            if ((h & 1) == 0) {
+                beta_row = right_task<T, TWM, NTL>(A, S, S32, sg, corner, ltid);
+            } else {
+                // row k of this step's right task (read by every wave of the lane in
+                // the previous phase) becomes (beta, 0, ..., 0)
+                if (defer_rowk && ltid <= sg.m)
+                    A[sg.k + (int64_t)(sg.p + ltid) * S] = static_cast<T>(ltid == 0 ? beta_row : 0.0);
+                left_task<T, TWM, NTL>(A, S, S32, sg, n, b, corner, stage, ltid);
+            }
         }
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();  // every wave of every lane has read its row k
-        if (active && (h & 1) == 0 && ltid <= sg.m)
-            A[sg.k + (int64_t)(sg.p + ltid) * S] = static_cast<T>(ltid == 0 ? beta_row : 0.0);
+        if (!defer_rowk) {
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();  // every wave of every lane has read its row k
+            if (active && (h & 1) == 0 && ltid <= sg.m)
+                A[sg.k + (int64_t)(sg.p + ltid) * S] = static_cast<T>(ltid == 0 ? beta_row : 0.0);
+        }
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();  // phase complete: its stores are visible inside the workgroup
 

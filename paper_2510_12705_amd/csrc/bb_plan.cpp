@@ -21,15 +21,25 @@ Plan make_plan(int64_t b, int tw) {
     return p;
 }
 
-int default_tw(int dtype) { return dtype == 0 ? 16 : 32; }
+int default_tw(int dtype) { (void)dtype; return 32; }
 
-int default_threads(int rows) {
+// threads per window: the power of two (64..256) that leaves at most one row of
+// the window per thread (FP64 storage: at most 1.25 rows)
+int default_threads(int rows, int dtype) {
     int nt = 64;
-    while (nt < rows && nt < 256) nt *= 2;
+    if (dtype == 0) {
+        while (nt * 5 < rows * 4 && nt < 256) nt *= 2;
+    } else {
+        while (nt < rows && nt < 256) nt *= 2;
+    }
     return nt;
 }
 
-int default_lanes(int threads_per_lane) { return std::max(1, std::min(8, 512 / threads_per_lane)); }
+// sweeps per workgroup: 256 threads per workgroup for FP64 storage, 512 otherwise
+int default_lanes(int threads_per_lane, int dtype) {
+    const int target = dtype == 0 ? 256 : 512;
+    return std::max(1, std::min(16, target / threads_per_lane));
+}
 
 int kernel_twm(int tw) { return tw <= 8 ? 8 : tw <= 16 ? 16 : 32; }
 

@@ -29,8 +29,8 @@ Plan make_plan(int64_t b, int tw);
 int min_lag(int c);
 
 int default_tw(int dtype);
-int default_threads(int rows);
-int default_lanes(int threads_per_lane);
+int default_threads(int rows, int dtype);
+int default_lanes(int threads_per_lane, int dtype);
 int kernel_twm(int tw);
 
 // Read + write bytes of the L-shaped window of every step, summed.
