@@ -113,6 +113,68 @@ __device__ __forceinline__ double lapy2(double a, double b) {
     return w * sqrt(1.0 + q * q);
 }
 
+// x_lane: lane t (0 <= t <= m) holds x_t.  Same reflector as house_uniform
+// below, generated through a per-wave LDS scratch `scr` of 2 (TWM + 1) doubles:
+// lane t writes x_t^2 and later x_t / (alpha - beta), every lane reads them back
+// (broadcast reads), so no lane-by-lane register broadcast is needed.  The
+// squares are summed left to right in the same order and operations as the
+// plain definition.  All 64 lanes of the wave must be active.
+template <int TWM, typename V>
+__device__ __forceinline__ void house_lds(double x_lane, int m, double* scr, V (&v)[TWM + 1], double& tau,
+                                          double& beta) {
+    static_assert(TWM < kWave, "one lane per entry");
+    constexpr double tsml = 0x1p-511, tbig = 0x1p486;
+    const int lane = threadIdx.x & (kWave - 1);
+    const double xm = mask_above(x_lane, m);  // lanes above m hold +0
+    double alpha = readlane_f64(xm, 0);
+    const double ax = fabs(xm);
+    // every nonzero |x_t| (1 <= t <= m) in [tsml, tbig]: plain sum of squares
+    const bool lane_ok = lane == 0 || ax == 0.0 || (ax >= tsml && ax <= tbig);
+    const bool mid = __ballot(!lane_ok) == 0;
+    if (lane <= TWM) scr[lane] = ax * ax;
+    __builtin_amdgcn_wave_barrier();
+    double amed = 0.0;
+#pragma unroll
+    for (int t = 1; t <= TWM; ++t) amed = amed + scr[t];
+    double xn = mid ? sqrt(amed) : nrm2_lanes_general(xm, m, 0);
+    v[0] = V(1);
+    if (xn == 0.0) {
+#pragma unroll
+        for (int t = 1; t <= TWM; ++t) v[t] = V(0);
+        tau = 0.0;
+        beta = alpha;
+        return;
+    }
+    double h = lapy2(alpha, xn);
+    double bt = alpha >= 0.0 ? -h : h;
+    constexpr double safmin = 2.2250738585072014e-308 / 2.220446049250313e-16;  // DBL_MIN / DBL_EPSILON
+    constexpr double rsafmn = 1.0 / safmin;
+    int knt = 0;
+    if (fabs(bt) < safmin) {
+        do {
+            ++knt;
+            bt = bt * rsafmn;
+            alpha = alpha * rsafmn;
+        } while (fabs(bt) < safmin && knt < 20);
+        xn = nrm2_lanes_general(xm, m, knt);
+        h = lapy2(alpha, xn);
+        bt = alpha >= 0.0 ? -h : h;
+    }
+    const double scal = 1.0 / (alpha - bt);
+    double xs = xm;  // this lane's x_t, rescaled like the reference (exact powers of two)
+#pragma unroll 1
+    for (int i = 0; i < knt; ++i) xs = xs * rsafmn;
+    V* sv = reinterpret_cast<V*>(scr + TWM + 1);
+    if (lane <= TWM) sv[lane] = static_cast<V>(xs * scal);  // x_t == 0 for t > m
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int t = 1; t <= TWM; ++t) v[t] = sv[t];
+    __builtin_amdgcn_wave_barrier();  // the scratch is rewritten by the next call
+    tau = (bt - alpha) / bt;
+    for (int i = 0; i < knt; ++i) bt = bt * safmin;
+    beta = bt;
+}
+
 // x_lane: lane t (0 <= t <= m) holds x_t.  On return v[0..TWM] holds the
 // reflector (v[0] = 1, v[t] = 0 for t > m), uniform across the wave.  The lane
 // values are re-read with readlane where needed rather than kept in an array,

@@ -289,7 +289,7 @@ __device__ __forceinline__ int sweep_halfsteps(int n, int b, int c, int r) { ret
 // phase barrier (every wave of the lane has read it by then).  Returns beta.
 template <typename T, int TWM, int NTL>
 __device__ __forceinline__ double right_task(T* __restrict__ A, int64_t S, int S32, StepGeom g,
-                                             typename Compute<T>::type* corner, int ltid) {
+                                             typename Compute<T>::type* corner, double* scr, int ltid) {
     using C = typename Compute<T>::type;
     constexpr int LDC = TWM + 1;
     const int k = g.k, p = g.p, m = g.m;
@@ -302,7 +302,7 @@ __device__ __forceinline__ double right_task(T* __restrict__ A, int64_t S, int S
     load_row<T, C, TWM>(av, base, S32, 1 + min(ri, rows - 1), m);
     C vs[TWM + 1];
     double taud, betad;
-    house_uniform<TWM>(xl, m, vs, taud, betad);
+    house_lds<TWM>(xl, m, scr, vs, taud, betad);
     const C tau = static_cast<C>(taud);
     while (ri < rows) {
         const int i = k + 1 + ri;
@@ -328,9 +328,13 @@ __device__ __forceinline__ double right_task(T* __restrict__ A, int64_t S, int S
 // segment update.  For 4- and 8-byte storage the block is filled by
 // global-to-LDS loads (no registers); columns p+1..p+m come from the corner.  A
 // wave exchanges data only with itself through its block (no barrier).
-// Fill a wave's LDS block with columns c0 .. c0+63 (those < cols) of the left
-// task's window; columns below m come from the corner.  4/8-byte storage: the
-// loads go straight to LDS and complete at the next s_waitcnt vmcnt.
+// Fill a wave's LDS block with columns c0 .. c0+63 of the left task's window
+// (slot e of the block holds column e / (TWM+1), row e % (TWM+1)).
+// 4/8-byte storage: one global-to-LDS dword load per slot dword.  Slots outside
+// the window (rows above m, columns at or beyond cols) load a clamped in-window
+// address instead of being masked: their LDS contents are never used.  Columns
+// below m live in the corner; they are copied by left_corner_in once the loads
+// have landed (a load landing later would overwrite them).
 template <typename T, int TWM>
 __device__ __forceinline__ void left_stage_in(const T* __restrict__ base, int S32, const typename Compute<T>::type* corner,
                                               typename Compute<T>::type* blk, int c0, int m, int cols, int lane) {
@@ -340,25 +344,27 @@ __device__ __forceinline__ void left_stage_in(const T* __restrict__ base, int S3
         static_assert(sizeof(T) == sizeof(C), "4/8-byte storage is computed in its own type");
         constexpr int DW = sizeof(T) / 4;  // dwords per element
         constexpr int PITCH = LDC * DW;    // dwords per column in the block
-        const uint32_t* gd = reinterpret_cast<const uint32_t*>(base);
+        constexpr int QC = kWave / PITCH, QW = kWave % PITCH;  // slot advance per instruction
+        const char* gb = reinterpret_cast<const char*>(base);
         uint32_t* bd = reinterpret_cast<uint32_t*>(blk);
+        const int wlim = (m + 1) * DW - 1;  // last dword of a column run
+        const int clim = cols - 1 - c0;     // last column of the window, relative to c0
+        const int colS = S32 * DW;          // dwords between columns
+        int col = lane / PITCH, w = lane - col * PITCH;
 #pragma unroll 4
         for (int u = 0; u < PITCH; ++u) {
-            const int j = u * kWave + lane;
-            const int col = j / PITCH, w = j - col * PITCH;
-            const int ci = c0 + col;
-            if (w < (m + 1) * DW && ci >= m && ci < cols)
-                dma_dword(reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(gd) +
-                                                            static_cast<uint32_t>(((1 + ci) * S32 * DW + w) * 4)),
-                          bd + u * kWave);
-        }
-        if (c0 + lane < m) {
-#pragma unroll
-            for (int t = 0; t <= TWM; ++t)
-                if (t <= m) blk[lane * LDC + t] = corner[t * LDC + c0 + lane + 1];
+            const int ce = min(col, clim), we = min(w, wlim);
+            const uint32_t off = static_cast<uint32_t>(((1 + c0 + ce) * colS + we) * 4);
+            dma_dword(reinterpret_cast<const uint32_t*>(gb + off), bd + u * kWave);
+            col += QC;
+            w += QW;
+            if (w >= PITCH) {
+                w -= PITCH;
+                ++col;
+            }
         }
     } else {
-#pragma unroll
+#pragma unroll 4
         for (int u = 0; u < LDC; ++u) {
             const int e = u * kWave + lane;
             const int col = e / LDC, t = e - col * LDC;
@@ -366,6 +372,21 @@ __device__ __forceinline__ void left_stage_in(const T* __restrict__ base, int S3
             C v = C(0);
             if (t <= m && ci < cols) v = ci < m ? corner[t * LDC + ci + 1] : to_c(at(const_cast<T*>(base), (1 + ci) * S32 + t));
             blk[e] = v;
+        }
+    }
+}
+
+// Columns below m of the first block come from the corner (4/8-byte storage;
+// call after the block's loads completed).
+template <typename T, int TWM>
+__device__ __forceinline__ void left_corner_in(const typename Compute<T>::type* corner,
+                                               typename Compute<T>::type* blk, int c0, int m, int lane) {
+    constexpr int LDC = TWM + 1;
+    if constexpr (sizeof(T) >= 4) {
+        if (c0 + lane < m) {
+#pragma unroll
+            for (int t = 0; t <= TWM; ++t)
+                if (t <= m) blk[lane * LDC + t] = corner[t * LDC + c0 + lane + 1];
         }
     }
 }
@@ -382,7 +403,7 @@ __device__ __forceinline__ void left_stage_in(const T* __restrict__ base, int S3
 template <typename T, int TWM, int NTL>
 __device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32, StepGeom g, int n, int b,
                                           const typename Compute<T>::type* corner,
-                                          typename Compute<T>::type* stage, int ltid) {
+                                          typename Compute<T>::type* stage, double* scr, int ltid) {
     using C = typename Compute<T>::type;
     constexpr int LDC = TWM + 1;
     const int p = g.p, m = g.m;
@@ -397,11 +418,14 @@ __device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32,
     if (c_first < cols) left_stage_in<T, TWM>(base, S32, corner, blk, c_first, m, cols, lane);
     C vs[TWM + 1];
     double taud, betad;
-    house_uniform<TWM>(xl, m, vs, taud, betad);
+    house_lds<TWM>(xl, m, scr, vs, taud, betad);
     const C tau = static_cast<C>(taud);
+    const int tlim = m, clim0 = cols;
     for (int c0 = c_first; c0 < cols; c0 += NTL) {
         if (c0 != c_first) left_stage_in<T, TWM>(base, S32, corner, blk, c0, m, cols, lane);
         __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+        left_corner_in<T, TWM>(corner, blk, c0, m, lane);
         __builtin_amdgcn_wave_barrier();
         C av[TWM + 1];
 #pragma unroll
@@ -410,21 +434,40 @@ __device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32,
 #pragma unroll
         for (int t = 0; t <= TWM; ++t) blk[lane * LDC + t] = av[t];
         __builtin_amdgcn_wave_barrier();
+        // write back: slot e = u*kWave + lane holds column col, row t
+        {
+            constexpr int QC = kWave / LDC, QW = kWave % LDC;
+            int col = lane / LDC, t = lane - col * LDC;
+            const int cmax = clim0 - c0;
 #pragma unroll 4
-        for (int u = 0; u < LDC; ++u) {
-            const int e = u * kWave + lane;
-            const int col = e / LDC, t = e - col * LDC;
-            const int ci = c0 + col;
-            if (t <= m && ci < cols) at(base, (1 + ci) * S32 + t) = static_cast<T>(blk[e]);
+            for (int u = 0; u < LDC; ++u) {
+                if (t <= tlim && col < cmax) at(base, (1 + c0 + col) * S32 + t) = static_cast<T>(blk[u * kWave + lane]);
+                col += QC;
+                t += QW;
+                if (t >= LDC) {
+                    t -= LDC;
+                    ++col;
+                }
+            }
         }
         __builtin_amdgcn_wave_barrier();
     }
     if (ltid <= m) at(base, ltid) = static_cast<T>(ltid == 0 ? betad : 0.0);
 }
 
-// LDS of one lane: its (TWM+1)^2 corner, then one staging block per wave
-template <int TWM, int NTL>
-constexpr int lane_lds_elems() { return (TWM + 1) * (TWM + 1) + NTL * (TWM + 1); }
+// LDS of one lane (bytes): its (TWM+1)^2 corner and one staging block of
+// kWave (TWM+1) elements per wave, in the compute type; then per wave a
+// reflector scratch of 2 (TWM+1) doubles.
+constexpr size_t lds_align(size_t x) { return (x + 15) / 16 * 16; }
+template <typename C, int TWM, int NTL>
+struct LaneLds {
+    static constexpr int LDC = TWM + 1;
+    static constexpr size_t corner = 0;
+    static constexpr size_t stage = lds_align(sizeof(C) * LDC * LDC);
+    static constexpr size_t scratch = stage + lds_align(sizeof(C) * NTL * LDC);
+    static constexpr size_t scratch_per_wave = sizeof(double) * 2 * LDC;
+    static constexpr size_t bytes = lds_align(scratch + scratch_per_wave * (NTL / kWave));
+};
 
 // largest workgroup a variant is compiled for (wider windows need more registers)
 template <int TWM>
@@ -470,15 +513,18 @@ struct GroupArgs {
 // runs half-step P - H*g of sweep r0+g; see bb_stage below.  Returns false if the
 // pipeline was aborted.
 template <typename T, int TWM, int NTL>
-__device__ bool run_group(const GroupArgs& ga, typename Compute<T>::type* corners, int* s_ok) {
+__device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
     using C = typename Compute<T>::type;
     constexpr int LDC = TWM + 1;
     const int tid = threadIdx.x;
     const int G = blockDim.x / NTL;
     const int g = tid / NTL;
     const int ltid = tid - g * NTL;
-    C* corner = corners + g * (LDC * LDC);
-    C* stage = corners + G * (LDC * LDC) + g * (NTL * LDC);
+    using Lay = LaneLds<C, TWM, NTL>;
+    unsigned char* my = lds + g * Lay::bytes;
+    C* corner = reinterpret_cast<C*>(my + Lay::corner);
+    C* stage = reinterpret_cast<C*>(my + Lay::stage);
+    double* scr = reinterpret_cast<double*>(my + Lay::scratch + Lay::scratch_per_wave * ((tid - g * NTL) / kWave));
     T* __restrict__ A = reinterpret_cast<T*>(ga.A);
     const int64_t S = ga.S;
     const int S32 = (int)ga.S;
@@ -538,13 +584,13 @@ __device__ bool run_group(const GroupArgs& ga, typename Compute<T>::type* corner
         if (active) {
             sg = step_geom(n, b, tw, c, r, h >> 1);
             if ((h & 1) == 0) {
-                beta_row = right_task<T, TWM, NTL>(A, S, S32, sg, corner, ltid);
+                beta_row = right_task<T, TWM, NTL>(A, S, S32, sg, corner, scr, ltid);
             } else {
                 // row k of this step's right task (read by every wave of the lane in
                 // the previous phase) becomes (beta, 0, ..., 0)
                 if (defer_rowk && ltid <= sg.m)
                     A[sg.k + (int64_t)(sg.p + ltid) * S] = static_cast<T>(ltid == 0 ? beta_row : 0.0);
-                left_task<T, TWM, NTL>(A, S, S32, sg, n, b, corner, stage, ltid);
+                left_task<T, TWM, NTL>(A, S, S32, sg, n, b, corner, stage, scr, ltid);
             }
         }
         if (!defer_rowk) {
@@ -592,7 +638,7 @@ template <typename T, int TWM, int NTL>
 __global__ __launch_bounds__(max_threads<TWM>()) void bb_stage(StageArgs a) {
     using C = typename Compute<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    C* corners = reinterpret_cast<C*>(smem_raw);  // G blocks of (TWM+1)^2
+    unsigned char* lds = smem_raw;  // G lane blocks
     __shared__ int s_group;
     __shared__ int s_ok;
     const int G = blockDim.x / NTL;
@@ -622,7 +668,7 @@ __global__ __launch_bounds__(max_threads<TWM>()) void bb_stage(StageArgs a) {
         ga.abort_flag = a.abort_flag;
         ga.err_word = a.err_word;
         ga.spin_limit = a.spin_limit;
-        if (!run_group<T, TWM, NTL>(ga, corners, &s_ok)) return;
+        if (!run_group<T, TWM, NTL>(ga, lds, &s_ok)) return;
     }
 }
 
@@ -638,7 +684,7 @@ template <typename T, int TWM, int NTL>
 __global__ __launch_bounds__(max_threads<TWM>()) void bb_stage_batched(BatchArgs a) {
     using C = typename Compute<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    C* corners = reinterpret_cast<C*>(smem_raw);
+    unsigned char* lds = smem_raw;
     __shared__ int s_task;
     __shared__ int s_ok;
     __shared__ float s_red[32];
@@ -710,7 +756,7 @@ __global__ __launch_bounds__(max_threads<TWM>()) void bb_stage_batched(BatchArgs
                 __syncthreads();
             }
         }
-        if (!run_group<T, TWM, NTL>(ga, corners, &s_ok)) return;
+        if (!run_group<T, TWM, NTL>(ga, lds, &s_ok)) return;
     }
 }
 
@@ -824,7 +870,7 @@ hipError_t launch_fill(int* p, int64_t count, int value, hipStream_t st) {
 template <typename T, int TWM, int NTL>
 static hipError_t launch_stage_t(const StageArgs& a, int lanes, int grid, hipStream_t st) {
     using C = typename Compute<T>::type;
-    const size_t smem = (size_t)lanes * lane_lds_elems<TWM, NTL>() * sizeof(C);
+    const size_t smem = (size_t)lanes * LaneLds<C, TWM, NTL>::bytes;
     hipLaunchKernelGGL((bb_stage<T, TWM, NTL>), dim3(grid), dim3(NTL * lanes), smem, st, a);
     return hipGetLastError();
 }
@@ -852,7 +898,7 @@ static hipError_t launch_stage_tw(const StageArgs& a, int twm, int ntl, int lane
 template <typename T, int TWM, int NTL>
 static hipError_t launch_batched_t(const BatchArgs& a, int lanes, int grid, hipStream_t st) {
     using C = typename Compute<T>::type;
-    const size_t smem = (size_t)lanes * lane_lds_elems<TWM, NTL>() * sizeof(C);
+    const size_t smem = (size_t)lanes * LaneLds<C, TWM, NTL>::bytes;
     hipLaunchKernelGGL((bb_stage_batched<T, TWM, NTL>), dim3(grid), dim3(NTL * lanes), smem, st, a);
     return hipGetLastError();
 }
@@ -925,8 +971,12 @@ hipError_t launch_extract_batched(int dtype, const BatchMatrix* mats, int count,
 int stage_max_threads(int twm) { return twm >= 16 ? max_threads<16>() : max_threads<8>(); }
 
 size_t stage_lds_bytes(int dtype, int twm, int ntl, int lanes) {
+    // same layout as LaneLds<C, TWM, NTL>
     const size_t c = dtype == 0 ? sizeof(double) : sizeof(float);
-    return (size_t)lanes * ((size_t)(twm + 1) * (twm + 1) + (size_t)ntl * (twm + 1)) * c;
+    const size_t ldc = (size_t)twm + 1;
+    const size_t stage = lds_align(c * ldc * ldc);
+    const size_t scratch = stage + lds_align(c * (size_t)ntl * ldc);
+    return (size_t)lanes * lds_align(scratch + sizeof(double) * 2 * ldc * (size_t)(ntl / kWave));
 }
 
 hipError_t launch_stage(int dtype, const StageArgs& a, int twm, int ntl, int lanes, int grid, hipStream_t st) {
