@@ -172,7 +172,12 @@ def main():
                      "avg_launch_ms": round(avg_launch_s * 1e3, 4)},
         "alg_bytes": alg64,
         "pct_roofline_whole_call": round(100.0 * alg64 / (ms64 / 1e3) / 1e9 / PEAK_HBM_GBPS, 2),
+        "tuned_schedule_bytes": bb.model_bytes(n, b, 8, p.tw),
+        "compulsory_bytes": float(n * (b + 1) * 8 + (2 * n - 1) * 8),
     }
+    crit = sum(lag * (n - c) for (_, _, c, lag) in bb.plan(b, p.tw))
+    out["critical_half_steps"] = crit
+    out["us_per_critical_half_step"] = round(ms64 * 1e3 / crit, 4)
     if not args.no_fp32:
         band32 = band64.to(torch.float32)
         ms32, st32, l32, _, _ = time_reductions(bb, torch, band32, n, b, args.steps, args.warmup, "fp32")
