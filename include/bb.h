@@ -71,6 +71,12 @@ enum {
  *                      stage uses max(lag, smallest safe lag of that stage), so
  *                      0 selects the smallest safe value (bb_min_lag) and a
  *                      larger value only delays sweeps (results are unchanged).
+ *   xcd_run            consecutive sweep groups placed on one XCD (accelerator
+ *                      die with its own L2) before moving to the next (1..4096;
+ *                      0 = automatic, 8).  Hand-over inside a run stays in one
+ *                      L2; only run boundaries write back / invalidate it.
+ *                      Results do not depend on it.  bb_reduce only; the
+ *                      batched form claims tasks in one global order.
  */
 typedef struct {
     int tw;
@@ -78,6 +84,7 @@ typedef struct {
     int sweeps_per_group;
     int groups_per_cu;
     int lag;
+    int xcd_run;
 } bb_params_t;
 
 /*

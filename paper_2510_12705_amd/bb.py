@@ -28,11 +28,12 @@ class BBError(RuntimeError):
 
 class Params(ctypes.Structure):
     _fields_ = [("tw", ctypes.c_int), ("threads_per_window", ctypes.c_int),
-                ("sweeps_per_group", ctypes.c_int), ("groups_per_cu", ctypes.c_int), ("lag", ctypes.c_int)]
+                ("sweeps_per_group", ctypes.c_int), ("groups_per_cu", ctypes.c_int), ("lag", ctypes.c_int),
+                ("xcd_run", ctypes.c_int)]
 
     def __repr__(self):
-        return "Params(tw=%d, threads_per_window=%d, sweeps_per_group=%d, groups_per_cu=%d, lag=%d)" % (
-            self.tw, self.threads_per_window, self.sweeps_per_group, self.groups_per_cu, self.lag)
+        return "Params(tw=%d, threads_per_window=%d, sweeps_per_group=%d, groups_per_cu=%d, lag=%d, xcd_run=%d)" % (
+            self.tw, self.threads_per_window, self.sweeps_per_group, self.groups_per_cu, self.lag, self.xcd_run)
 
 
 def _load():
@@ -144,8 +145,8 @@ def bb_reduce_batched(bands, ns, bs, ds=None, es=None, stream=None):
     return [x[:n] for x, n in zip(ds, ns)], [x[:max(n - 1, 0)] for x, n in zip(es, ns)]
 
 
-def set_params(tw=0, threads_per_window=0, sweeps_per_group=0, groups_per_cu=0, lag=0):
-    p = Params(tw, threads_per_window, sweeps_per_group, groups_per_cu, lag)
+def set_params(tw=0, threads_per_window=0, sweeps_per_group=0, groups_per_cu=0, lag=0, xcd_run=0):
+    p = Params(tw, threads_per_window, sweeps_per_group, groups_per_cu, lag, xcd_run)
     _check(lib.bb_set_params(ctypes.byref(p)), "bb_set_params")
 
 

@@ -18,16 +18,19 @@
 
 namespace {
 
+constexpr int kMaxXcd = 16;  // per-XCD claim counters kept per stage
+
 struct DeviceState {
     bool init = false;
     int cus = 0;
     size_t lds_per_block = 65536;  // largest dynamic LDS allocation of one workgroup
+    int nxcd = 1;                  // XCDs (accelerator complex dies), each with its own L2
     int* err_host = nullptr;  // host-mapped error word
     int* err_dev = nullptr;
 };
 
 std::mutex g_mu;
-bb_params_t g_params = {0, 0, 0, 0, 0};
+bb_params_t g_params = {0, 0, 0, 0, 0, 0};
 std::vector<DeviceState> g_dev;
 
 struct Timing {
@@ -56,6 +59,9 @@ int device_state(DeviceState** out) {
         if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return BB_ERR_NODEVICE;
         s.cus = prop.multiProcessorCount;
         if (prop.sharedMemPerBlock > 0) s.lds_per_block = prop.sharedMemPerBlock;
+        int nx = 1;
+        if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, dev) == hipSuccess && nx >= 1)
+            s.nxcd = std::min(nx, (int)kMaxXcd);
         if (hipHostMalloc((void**)&s.err_host, sizeof(int), hipHostMallocMapped | hipHostMallocCoherent) !=
             hipSuccess)
             return BB_ERR_NOMEM;
@@ -81,7 +87,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // caller (or an autotuned entry) they are re-derived for every stage from its
 // window height (stage_shape).
 struct Launch {
-    int tw, ntl, lanes, groups_per_cu, lag;
+    int tw, ntl, lanes, groups_per_cu, lag, xcd_run;
     bool ntl_fixed, lanes_fixed;
     size_t lds_limit;
 };
@@ -104,6 +110,7 @@ Launch resolve(int64_t n, int64_t b, int dtype, size_t lds_limit = 65536) {
     L.lds_limit = lds_limit;
     L.groups_per_cu = p.groups_per_cu ? p.groups_per_cu : cached ? t.groups_per_cu : 2;
     L.lag = p.lag;
+    L.xcd_run = p.xcd_run ? p.xcd_run : 8;
     // fit the workgroup's LDS (corners + staging blocks) and thread limits
     const int twm = bbp::kernel_twm(L.tw);
     while (L.lanes > 1 && bbk::stage_lds_bytes(dtype, twm, L.ntl, L.lanes) > lds_limit) --L.lanes;
@@ -126,8 +133,9 @@ struct Workspace {
     size_t band_bytes = 0, counter_bytes = 0, total = 0;
     int64_t ldw = 0, uo = 0, max_sweeps = 0;
     int nstages = 0;
-    // counter words: progress[nstages][max_sweeps] | claim, abort per stage | FP16
-    // amax per stage | FP16 exps[nstages + 1]; all zero-initialised per call
+    // counter words: progress[nstages][max_sweeps] | per stage kMaxXcd claim words and
+    // an abort word | FP16 amax per stage | FP16 exps[nstages + 1]; all zero-initialised
+    // per call
     int64_t off_claim = 0, off_amax = 0, off_exps = 0, ncounters = 0;
 };
 
@@ -141,7 +149,7 @@ Workspace workspace_layout(int64_t n, int64_t b, int dtype, int tw) {
     w.max_sweeps = std::max<int64_t>(n, 1);
     w.band_bytes = align_up((size_t)(n * w.ldw) * elem_size(dtype), 256);
     w.off_claim = w.nstages * w.max_sweeps;
-    w.off_amax = w.off_claim + 2 * w.nstages;
+    w.off_amax = w.off_claim + (kMaxXcd + 1) * w.nstages;
     w.off_exps = w.off_amax + w.nstages;
     w.ncounters = w.off_exps + w.nstages + 1;
     w.counter_bytes = align_up(sizeof(int) * (size_t)w.ncounters, 256);
@@ -407,10 +415,12 @@ int bb_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, int64_t 
         a.H = std::max(sg.lag, L.lag);
         a.nsweeps = (int)std::max<int64_t>(n - sg.c - 1, 0);
         a.progress = counters + s * ws.max_sweeps;
-        a.claim = counters + ws.off_claim + 2 * s;
-        a.abort_flag = a.claim + 1;
+        a.claim = counters + ws.off_claim + (kMaxXcd + 1) * s;
+        a.abort_flag = a.claim + kMaxXcd;
         a.err_word = ds->err_dev;
         a.spin_limit = spin_limit();
+        a.nxcd = ds->nxcd > 1 && L.xcd_run > 0 ? ds->nxcd : 0;
+        a.xcd_run = std::max(L.xcd_run, 1);
         if (a.nsweeps == 0) continue;
         if (dtype == BB_F16)
             rc = check_hip(bbk::launch_f16_rescale(W, n * ws.ldw, f16_amax + s, f16_exps, s, st));
@@ -481,7 +491,7 @@ int bb_reduce_batched(int64_t count, const int64_t* n, const int64_t* b, bb_dtyp
 }
 
 int bb_set_params(const bb_params_t* p) {
-    bb_params_t q = {0, 0, 0, 0, 0};
+    bb_params_t q = {0, 0, 0, 0, 0, 0};
     if (p) {
         if (p->tw < 0 || p->tw > bbp::kMaxTW) return -1;
         if (p->threads_per_window != 0 && p->threads_per_window != 64 && p->threads_per_window != 128 &&
@@ -492,6 +502,7 @@ int bb_set_params(const bb_params_t* p) {
             return -1;
         if (p->groups_per_cu < 0 || p->groups_per_cu > 16) return -1;
         if (p->lag < 0 || p->lag > 64) return -1;
+        if (p->xcd_run < 0 || p->xcd_run > 4096) return -1;
         q = *p;
     }
     std::lock_guard<std::mutex> lk(g_mu);
@@ -599,6 +610,6 @@ extern "C" int bb_autotune(int64_t n, int64_t b, bb_dtype_t dtype, void* stream,
     DeviceState* ds = nullptr;
     const size_t lds = device_state(&ds) == BB_OK ? ds->lds_per_block : 65536;
     Launch L = resolve(n, std::min<int64_t>(b, std::max<int64_t>(n - 1, 0)), dtype, lds);
-    if (out) *out = bb_params_t{L.tw, L.ntl, L.lanes, L.groups_per_cu, L.lag};
+    if (out) *out = bb_params_t{L.tw, L.ntl, L.lanes, L.groups_per_cu, L.lag, L.xcd_run};
     return BB_OK;
 }

@@ -15,10 +15,13 @@ struct StageArgs {
     int nsweeps;        // n - c - 1 (sweeps that exist in this stage)
     int* progress;      // [nsweeps] half-step counters (zeroed before launch); only the
                         // last sweep of each group of consecutive sweeps is written
-    int* claim;         // [1] next group of sweeps to hand out (zeroed before launch)
+    int* claim;         // [1] next group of sweeps to hand out (zeroed before launch); with
+                        // nxcd > 0: [nxcd] per-XCD claim counters
     int* abort_flag;    // [1] watchdog abort word (zeroed before launch)
     int* err_word;      // host-mapped error word
     unsigned spin_limit;
+    int nxcd;           // XCDs of the device (0: groups are claimed in one global order)
+    int xcd_run;        // consecutive groups placed on one XCD (>= 1; used when nxcd > 0)
 };
 
 // ---- ragged batch ----

@@ -474,7 +474,8 @@ template <int TWM>
 constexpr int max_threads() { return TWM >= 16 ? 512 : 1024; }
 
 // Thread 0 only: spin until *flag >= need (or abort / watchdog).  Returns the value
-// seen (>= need) or -1 on abort; ends with an agent-scope acquire.
+// seen (>= need) or -1 on abort; ends with an agent-scope acquire (invalidates this
+// CU's L1 and the stale lines of this XCD's L2).
 __device__ __forceinline__ int poll_ge(const int* flag, int need, int* abort_flag, int* err_word, unsigned spin_limit) {
     unsigned spins = 0;
     int v;
@@ -507,6 +508,10 @@ struct GroupArgs {
     int* abort_flag;
     int* err_word;
     unsigned spin_limit;
+    bool next_local;         // the next group runs on this XCD (shares its L2): the release
+                             // only needs this group's stores completed, which every wave
+                             // waits for before the phase barrier; otherwise the release
+                             // also writes this XCD's L2 back (agent scope)
 };
 
 // Executed by the whole workgroup (G lanes of NTL threads).  In phase P lane g
@@ -606,7 +611,7 @@ __device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
         if (tid == 0) {
             const int done_last = min(max(P + 1 - H * (nl - 1), 0), len_last);
             if (done_last > published) {
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                if (!ga.next_local) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 __hip_atomic_store(ga.last, done_last, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 published = done_last;
             }
@@ -618,7 +623,7 @@ __device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
         if (ok && ga.prev && known < kDone && poll_ge(ga.prev, kDone, ga.abort_flag, ga.err_word, ga.spin_limit) < 0)
             ok = 0;
         if (ok) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (!ga.next_local) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __hip_atomic_store(ga.last, kDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         *s_ok = ok;
@@ -643,9 +648,28 @@ __global__ __launch_bounds__(max_threads<TWM>()) void bb_stage(StageArgs a) {
     __shared__ int s_ok;
     const int G = blockDim.x / NTL;
     const int ngroups = (a.nsweeps + G - 1) / G;
+    // XCD-aware order: runs of xcd_run consecutive groups are assigned to the XCDs
+    // round-robin and each XCD claims its own groups in increasing order, so the
+    // hand-over inside a run stays in one L2.  The smallest unfinished group is
+    // always claimable (its XCD claimed every earlier group of its sequence), so
+    // the claim order cannot deadlock while every XCD holds a workgroup.
+    const int Q = a.xcd_run;
+    int xcd = 0;
+    if (a.nxcd > 0) {
+        unsigned id;
+        asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(id));
+        xcd = (int)((id & 0xfu) % (unsigned)a.nxcd);
+    }
     for (;;) {
         if (threadIdx.x == 0) {
-            int q = atomicAdd(a.claim, 1);
+            int q;
+            if (a.nxcd > 0) {
+                const int k = atomicAdd(a.claim + xcd, 1);
+                const int64_t qq = ((int64_t)(k / Q) * a.nxcd + xcd) * Q + (k % Q);
+                q = qq < ngroups ? (int)qq : ngroups;
+            } else {
+                q = atomicAdd(a.claim, 1);
+            }
             if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) q = ngroups;
             s_group = q;
         }
@@ -668,6 +692,7 @@ __global__ __launch_bounds__(max_threads<TWM>()) void bb_stage(StageArgs a) {
         ga.abort_flag = a.abort_flag;
         ga.err_word = a.err_word;
         ga.spin_limit = a.spin_limit;
+        ga.next_local = a.nxcd > 0 && (q + 1) % Q != 0;
         if (!run_group<T, TWM, NTL>(ga, lds, &s_ok)) return;
     }
 }
@@ -717,6 +742,7 @@ __global__ __launch_bounds__(max_threads<TWM>()) void bb_stage_batched(BatchArgs
             ga.stage_prev = a.progress + Sp.prog_off + Sp.ngroups - 1;
         }
         ga.last = a.progress + St.prog_off + tk.group;
+        ga.next_local = false;
         ga.abort_flag = a.abort_flag;
         ga.err_word = a.err_word;
         ga.spin_limit = a.spin_limit;

@@ -58,15 +58,17 @@ def test_argument_validation_without_device():
 
 
 def test_params_roundtrip_and_rejection():
-    bb.set_params(tw=8, threads_per_window=128, sweeps_per_group=4, groups_per_cu=2, lag=0)
+    bb.set_params(tw=8, threads_per_window=128, sweeps_per_group=4, groups_per_cu=2, lag=0, xcd_run=5)
     p = bb.get_params()
-    assert (p.tw, p.threads_per_window, p.sweeps_per_group, p.groups_per_cu, p.lag) == (8, 128, 4, 2, 0)
+    assert (p.tw, p.threads_per_window, p.sweeps_per_group, p.groups_per_cu, p.lag, p.xcd_run) == (8, 128, 4, 2, 0, 5)
     with pytest.raises(bb.BBError):
         bb.set_params(tw=40)
     with pytest.raises(bb.BBError):
         bb.set_params(threads_per_window=96)
     with pytest.raises(bb.BBError):
         bb.set_params(threads_per_window=256, sweeps_per_group=8)   # 2048 threads
+    with pytest.raises(bb.BBError):
+        bb.set_params(xcd_run=-1)
     p2 = bb.get_params()
     assert p2.tw == 8  # a rejected call leaves the state unchanged
     bb.reset_params()

@@ -110,6 +110,18 @@ def test_schedule_independence_bitwise(bb, gpc, lanes):
     assert np.array_equal(d, ref[0]) and np.array_equal(e, ref[1])
 
 
+@pytest.mark.parametrize("xcd_run", [1, 3, 64])
+def test_xcd_run_is_bitwise_identical(bb, xcd_run):
+    """Placement of sweep groups on XCDs (and the cache scope of the hand-over it
+    implies) does not change a bit of the result."""
+    n, b, tw = 1500, 48, 16
+    _say("case n=%d b=%d xcd_run=%d" % (n, b, xcd_run))
+    band = inputs.band_normal(n, b, seed=21)
+    d, e = gpu_reduce(bb, band, n, b, tw=tw, xcd_run=xcd_run)
+    do, eo = oracle.reduce(band, n, b, tw)
+    assert np.array_equal(d, do) and np.array_equal(e, eo)
+
+
 def test_larger_lag_is_bitwise_identical(bb):
     n, b, tw = 1200, 40, 8
     band = inputs.band_normal(n, b, seed=5)
