@@ -146,17 +146,14 @@ __device__ __forceinline__ P* wave_uniform(P* ptr) {
     return reinterpret_cast<P*>((static_cast<uint64_t>(hi) << 32) | lo);
 }
 
+// a value known to be equal on every lane of the wave, moved to a scalar register
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
 template <typename T>
 __device__ __forceinline__ T& at(T* base, int off) {
     return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + static_cast<uint32_t>(off) * sizeof(T));
 }
 
-typedef __attribute__((address_space(3))) void* lds_void_ptr;
-
-// one dword per thread from global memory straight into LDS at lds + 4 * lane
-__device__ __forceinline__ void dma_dword(const uint32_t* g, uint32_t* lds) {
-    __builtin_amdgcn_global_load_lds(g, (lds_void_ptr)(lds), 4, 0, 0);
-}
 
 // ---------------------------------------------------------------------------
 // Householder application to one row / column segment of m+1 values held in
@@ -292,7 +289,7 @@ __device__ __forceinline__ double right_task(T* __restrict__ A, int64_t S, int S
                                              typename Compute<T>::type* corner, double* scr, int ltid) {
     using C = typename Compute<T>::type;
     constexpr int LDC = TWM + 1;
-    const int k = g.k, p = g.p, m = g.m;
+    const int k = uni(g.k), p = uni(g.p), m = uni(g.m);  // a wave never spans two sweeps
     const int lane = ltid & (kWave - 1);
     const int rows = p + m - k;  // rows k+1 .. p+m
     T* base = wave_uniform(A + k + (int64_t)p * S);  // A(k, p)
@@ -321,132 +318,70 @@ __device__ __forceinline__ double right_task(T* __restrict__ A, int64_t S, int S
 
 // Left task of one lane: reflector from A[p..p+m, p] (held in the corner), applied
 // to rows p..p+m of columns p+1..L; writes column p as (beta, 0, ..., 0).
-// Each wave moves its columns through its own LDS block of kWave columns with a
-// pitch of TWM+1 elements: in global memory a column's m+1 rows are contiguous,
-// so the block is filled and written back as contiguous runs; each thread then
-// updates one column in registers with the same sequential dot as every other
-// segment update.  For 4- and 8-byte storage the block is filled by
-// global-to-LDS loads (no registers); columns p+1..p+m come from the corner.  A
-// wave exchanges data only with itself through its block (no barrier).
-// Fill a wave's LDS block with columns c0 .. c0+63 of the left task's window
-// (slot e of the block holds column e / (TWM+1), row e % (TWM+1)).
-// 4/8-byte storage: one global-to-LDS dword load per slot dword.  Slots outside
-// the window (rows above m, columns at or beyond cols) load a clamped in-window
-// address instead of being masked: their LDS contents are never used.  Columns
-// below m live in the corner; they are copied by left_corner_in once the loads
-// have landed (a load landing later would overwrite them).
-template <typename T, int TWM>
-__device__ __forceinline__ void left_stage_in(const T* __restrict__ base, int S32, const typename Compute<T>::type* corner,
-                                              typename Compute<T>::type* blk, int c0, int m, int cols, int lane) {
-    using C = typename Compute<T>::type;
-    constexpr int LDC = TWM + 1;
-    if constexpr (sizeof(T) >= 4) {
-        static_assert(sizeof(T) == sizeof(C), "4/8-byte storage is computed in its own type");
-        constexpr int DW = sizeof(T) / 4;  // dwords per element
-        constexpr int PITCH = LDC * DW;    // dwords per column in the block
-        constexpr int QC = kWave / PITCH, QW = kWave % PITCH;  // slot advance per instruction
-        const char* gb = reinterpret_cast<const char*>(base);
-        uint32_t* bd = reinterpret_cast<uint32_t*>(blk);
-        const int wlim = (m + 1) * DW - 1;  // last dword of a column run
-        const int clim = cols - 1 - c0;     // last column of the window, relative to c0
-        const int colS = S32 * DW;          // dwords between columns
-        int col = lane / PITCH, w = lane - col * PITCH;
-#pragma unroll 4
-        for (int u = 0; u < PITCH; ++u) {
-            const int ce = min(col, clim), we = min(w, wlim);
-            const uint32_t off = static_cast<uint32_t>(((1 + c0 + ce) * colS + we) * 4);
-            dma_dword(reinterpret_cast<const uint32_t*>(gb + off), bd + u * kWave);
-            col += QC;
-            w += QW;
-            if (w >= PITCH) {
-                w -= PITCH;
-                ++col;
-            }
-        }
-    } else {
-#pragma unroll 4
-        for (int u = 0; u < LDC; ++u) {
-            const int e = u * kWave + lane;
-            const int col = e / LDC, t = e - col * LDC;
-            const int ci = c0 + col;
-            C v = C(0);
-            if (t <= m && ci < cols) v = ci < m ? corner[t * LDC + ci + 1] : to_c(at(const_cast<T*>(base), (1 + ci) * S32 + t));
-            blk[e] = v;
-        }
-    }
-}
-
-// Columns below m of the first block come from the corner (4/8-byte storage;
-// call after the block's loads completed).
-template <typename T, int TWM>
-__device__ __forceinline__ void left_corner_in(const typename Compute<T>::type* corner,
-                                               typename Compute<T>::type* blk, int c0, int m, int lane) {
-    constexpr int LDC = TWM + 1;
-    if constexpr (sizeof(T) >= 4) {
-        if (c0 + lane < m) {
-#pragma unroll
-            for (int t = 0; t <= TWM; ++t)
-                if (t <= m) blk[lane * LDC + t] = corner[t * LDC + c0 + lane + 1];
-        }
-    }
-}
-
-// Left task of one lane: reflector from A[p..p+m, p] (held in the corner), applied
-// to rows p..p+m of columns p+1..L; writes column p as (beta, 0, ..., 0).
-// Each wave moves its columns through its own LDS block of kWave columns with a
-// pitch of TWM+1 elements: in global memory a column's m+1 rows are contiguous,
-// so the block is filled and written back as contiguous runs; each thread then
-// updates one column in registers with the same sequential dot as every other
-// segment update.  The first block's loads are in flight while the reflector is
-// generated.  A wave exchanges data only with itself through its block (no
-// barrier).
+// Thread ci of the lane owns column p+1+ci (ci += NTL): its m+1 rows are
+// contiguous in memory, so it loads them directly (one base address, immediate
+// offsets; columns p+1..p+m come from the corner block instead).  The loads are in
+// flight while the reflector is generated.  The updated columns go through the
+// wave's LDS block (column-major, pitch TWM+1) and are written back as contiguous
+// runs across the wave, so the stores are coalesced.  A wave exchanges data only
+// with itself through its block (no barrier).
 template <typename T, int TWM, int NTL>
 __device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32, StepGeom g, int n, int b,
                                           const typename Compute<T>::type* corner,
                                           typename Compute<T>::type* stage, double* scr, int ltid) {
     using C = typename Compute<T>::type;
     constexpr int LDC = TWM + 1;
-    const int p = g.p, m = g.m;
+    const int p = uni(g.p), m = uni(g.m);  // a wave never spans two sweeps
     const int lane = ltid & (kWave - 1);
     const int wv = ltid / kWave;
-    const int L = min(p + m + b, n - 1);
-    const int cols = L - p;  // columns p+1 .. L; column p+1+ci starts at base + (1 + ci) * S
-    T* base = wave_uniform(A + p + (int64_t)p * S);  // A(p, p)
+    const int cols = min(p + m + b, n - 1) - p;  // columns p+1 .. L
+    T* base = wave_uniform(A + p + (int64_t)p * S);  // A(p, p); column p+1+ci starts at base + (1 + ci) * S
     C* blk = stage + wv * (kWave * LDC);
     const double xl = static_cast<double>(corner[min(lane, m) * LDC]);
+    C av[TWM + 1];
+    // column ci of this thread: global rows (clamped to the window), or the corner
+    auto load_cols = [&](int ci) {
+        const int cg = min(max(ci, m), cols - 1);  // an in-window column for every lane
+        const T* col = &at(base, (1 + cg) * S32);
+#pragma unroll
+        for (int t = 0; t <= TWM; ++t) av[t] = to_c(col[min(t, m)]);
+    };
+    int ci = wv * kWave + lane;
     const int c_first = wv * kWave;
-    if (c_first < cols) left_stage_in<T, TWM>(base, S32, corner, blk, c_first, m, cols, lane);
+    if (c_first < cols) load_cols(ci);
     C vs[TWM + 1];
     double taud, betad;
     house_lds<TWM>(xl, m, scr, vs, taud, betad);
     const C tau = static_cast<C>(taud);
-    const int tlim = m, clim0 = cols;
-    for (int c0 = c_first; c0 < cols; c0 += NTL) {
-        if (c0 != c_first) left_stage_in<T, TWM>(base, S32, corner, blk, c0, m, cols, lane);
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
-        left_corner_in<T, TWM>(corner, blk, c0, m, lane);
-        __builtin_amdgcn_wave_barrier();
-        C av[TWM + 1];
+    for (int c0 = c_first; c0 < cols; c0 += NTL, ci += NTL) {
+        if (c0 != c_first) load_cols(ci);
+        if (ci < m) {
 #pragma unroll
-        for (int t = 0; t <= TWM; ++t) av[t] = t <= m ? blk[lane * LDC + t] : C(0);
+            for (int t = 0; t <= TWM; ++t) av[t] = corner[t * LDC + ci + 1];
+        }
+#pragma unroll
+        for (int t = 0; t <= TWM; ++t) av[t] = t <= m ? av[t] : C(0);
         if (taud != 0.0) apply_segment<C, TWM>(av, vs, tau, m);
 #pragma unroll
         for (int t = 0; t <= TWM; ++t) blk[lane * LDC + t] = av[t];
         __builtin_amdgcn_wave_barrier();
-        // write back: slot e = u*kWave + lane holds column col, row t
+        // write back: slot e = u*kWave + lane holds column col, row t (pitch LDC);
+        // offsets advance incrementally (no multiplies)
         {
             constexpr int QC = kWave / LDC, QW = kWave % LDC;
             int col = lane / LDC, t = lane - col * LDC;
-            const int cmax = clim0 - c0;
+            const int cmax = cols - c0;
+            int off = (1 + c0 + col) * S32 + t;
 #pragma unroll 4
             for (int u = 0; u < LDC; ++u) {
-                if (t <= tlim && col < cmax) at(base, (1 + c0 + col) * S32 + t) = static_cast<T>(blk[u * kWave + lane]);
+                if (t <= m && col < cmax) at(base, off) = static_cast<T>(blk[u * kWave + lane]);
                 col += QC;
                 t += QW;
+                off += QC * S32 + QW;
                 if (t >= LDC) {
                     t -= LDC;
                     ++col;
+                    off += S32 - LDC;
                 }
             }
         }

@@ -23,22 +23,20 @@ Plan make_plan(int64_t b, int tw) {
 
 int default_tw(int dtype) { (void)dtype; return 32; }
 
-// threads per window: the power of two (64..256) that leaves at most one row of
-// the window per thread (FP64 storage: at most 1.25 rows)
+// threads per window: the smallest power of two (64..256) with one thread per row
+// of the window
 int default_threads(int rows, int dtype) {
+    (void)dtype;
     int nt = 64;
-    if (dtype == 0) {
-        while (nt * 5 < rows * 4 && nt < 256) nt *= 2;
-    } else {
-        while (nt < rows && nt < 256) nt *= 2;
-    }
+    while (nt < rows && nt < 256) nt *= 2;
     return nt;
 }
 
-// sweeps per workgroup: 256 threads per workgroup for FP64 storage, 512 otherwise
+// sweeps per workgroup: about 256 threads per workgroup (one wave per SIMD of a
+// CU for the widest windows; narrow windows group several sweeps)
 int default_lanes(int threads_per_lane, int dtype) {
-    const int target = dtype == 0 ? 256 : 512;
-    return std::max(1, std::min(16, target / threads_per_lane));
+    (void)dtype;
+    return std::max(1, std::min(16, 256 / threads_per_lane));
 }
 
 int kernel_twm(int tw) { return tw <= 8 ? 8 : tw <= 16 ? 16 : 32; }
