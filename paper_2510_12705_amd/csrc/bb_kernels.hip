@@ -138,20 +138,29 @@ __global__ void bb_fill_i32(int* __restrict__ p, int64_t count, int value) {
 // wave never spans two lanes), so it is moved to scalar registers and every
 // access becomes scalar base + 32-bit unsigned byte offset (one VGPR per address).
 // ---------------------------------------------------------------------------
+// Band pointers are kept in the global address space: generic (flat) accesses
+// would also count against the LDS wait counter, so every LDS wait would wait for
+// outstanding band loads as well.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> to_global(T* p) { return (gptr<T>)(p); }
+
 template <typename P>
-__device__ __forceinline__ P* wave_uniform(P* ptr) {
+__device__ __forceinline__ gptr<P> wave_uniform(P* ptr) {
     const uint64_t v = reinterpret_cast<uint64_t>(ptr);
     const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
     const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
-    return reinterpret_cast<P*>((static_cast<uint64_t>(hi) << 32) | lo);
+    return reinterpret_cast<gptr<P>>((static_cast<uint64_t>(hi) << 32) | lo);
 }
 
 // a value known to be equal on every lane of the wave, moved to a scalar register
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 template <typename T>
-__device__ __forceinline__ T& at(T* base, int off) {
-    return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + static_cast<uint32_t>(off) * sizeof(T));
+__device__ __forceinline__ gptr<T> at(gptr<T> base, int off) {
+    return reinterpret_cast<gptr<T>>(reinterpret_cast<gptr<char>>(base) + static_cast<uint32_t>(off) * sizeof(T));
 }
 
 
@@ -197,11 +206,11 @@ __device__ __forceinline__ void apply_segment(C (&av)[TWM + 1], const C (&vs)[TW
 // ---------------------------------------------------------------------------
 // `base` points at A(k, p) of the current step; in-window offsets fit in 32 bits.
 template <typename T, typename C, int TWM>
-__device__ __forceinline__ void load_row(C (&av)[TWM + 1], const T* __restrict__ base, int S, int di, int m) {
+__device__ __forceinline__ void load_row(C (&av)[TWM + 1], gptr<T> base, int S, int di, int m) {
     // A(k + di, p + t) = base[di + t * S]
 #pragma unroll
     for (int t = 0; t <= TWM; ++t) {
-        const C v = to_c(at(const_cast<T*>(base), di + min(t, m) * S));
+        const C v = to_c(*at(base, di + min(t, m) * S));
         av[t] = t <= m ? v : C(0);
     }
 }
@@ -210,38 +219,9 @@ __device__ __forceinline__ void load_row(C (&av)[TWM + 1], const T* __restrict__
 // clamped address of entry m first and is then overwritten by entry m itself
 // (stores of one thread to one address keep program order).
 template <typename T, typename C, int TWM>
-__device__ __forceinline__ void store_row(const C (&av)[TWM + 1], T* __restrict__ base, int S, int di, int m) {
+__device__ __forceinline__ void store_row(const C (&av)[TWM + 1], gptr<T> base, int S, int di, int m) {
 #pragma unroll
-    for (int t = TWM; t >= 0; --t) at(base, di + min(t, m) * S) = static_cast<T>(av[t]);
-}
-
-// column q = p + 1 + ci of rows p..p+m; columns p+1..p+m come from the LDS corner
-// `base` points at A(p, p); column q = p + 1 + ci starts at base + (1 + ci) * S.
-template <typename T, typename C, int TWM>
-__device__ __forceinline__ void load_col(C (&av)[TWM + 1], const T* __restrict__ base, int S, const C* corner, int ci,
-                                         int m) {
-    constexpr int LDC = TWM + 1;
-    if (ci < m) {
-#pragma unroll
-        for (int t = 0; t <= TWM; ++t) {
-            const C v = corner[min(t, m) * LDC + ci + 1];
-            av[t] = t <= m ? v : C(0);
-        }
-    } else {
-        const T* col = base + (1 + ci) * S;  // A(p + t, q) = col[t]
-#pragma unroll
-        for (int t = 0; t <= TWM; ++t) {
-            const C v = to_c(col[min(t, m)]);
-            av[t] = t <= m ? v : C(0);
-        }
-    }
-}
-
-template <typename T, typename C, int TWM>
-__device__ __forceinline__ void store_col(const C (&av)[TWM + 1], T* __restrict__ base, int S, int ci, int m) {
-    T* col = base + (1 + ci) * S;
-#pragma unroll
-    for (int t = TWM; t >= 0; --t) col[min(t, m)] = static_cast<T>(av[t]);
+    for (int t = TWM; t >= 0; --t) *at(base, di + min(t, m) * S) = static_cast<T>(av[t]);
 }
 
 // ---------------------------------------------------------------------------
@@ -292,8 +272,8 @@ __device__ __forceinline__ double right_task(T* __restrict__ A, int64_t S, int S
     const int k = uni(g.k), p = uni(g.p), m = uni(g.m);  // a wave never spans two sweeps
     const int lane = ltid & (kWave - 1);
     const int rows = p + m - k;  // rows k+1 .. p+m
-    T* base = wave_uniform(A + k + (int64_t)p * S);  // A(k, p)
-    const double xl = static_cast<double>(at(base, min(lane, m) * S32));
+    gptr<T> base = wave_uniform(A + k + (int64_t)p * S);  // A(k, p)
+    const double xl = static_cast<double>(*at(base, min(lane, m) * S32));
     int ri = ltid;
     C av[TWM + 1];
     load_row<T, C, TWM>(av, base, S32, 1 + min(ri, rows - 1), m);
@@ -335,14 +315,14 @@ __device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32,
     const int lane = ltid & (kWave - 1);
     const int wv = ltid / kWave;
     const int cols = min(p + m + b, n - 1) - p;  // columns p+1 .. L
-    T* base = wave_uniform(A + p + (int64_t)p * S);  // A(p, p); column p+1+ci starts at base + (1 + ci) * S
+    gptr<T> base = wave_uniform(A + p + (int64_t)p * S);  // A(p, p); column p+1+ci starts at base + (1 + ci) * S
     C* blk = stage + wv * (kWave * LDC);
     const double xl = static_cast<double>(corner[min(lane, m) * LDC]);
     C av[TWM + 1];
     // column ci of this thread: global rows (clamped to the window), or the corner
     auto load_cols = [&](int ci) {
         const int cg = min(max(ci, m), cols - 1);  // an in-window column for every lane
-        const T* col = &at(base, (1 + cg) * S32);
+        const gptr<T> col = at(base, (1 + cg) * S32);
 #pragma unroll
         for (int t = 0; t <= TWM; ++t) av[t] = to_c(col[min(t, m)]);
     };
@@ -374,7 +354,7 @@ __device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32,
             int off = (1 + c0 + col) * S32 + t;
 #pragma unroll 4
             for (int u = 0; u < LDC; ++u) {
-                if (t <= m && col < cmax) at(base, off) = static_cast<T>(blk[u * kWave + lane]);
+                if (t <= m && col < cmax) *at(base, off) = static_cast<T>(blk[u * kWave + lane]);
                 col += QC;
                 t += QW;
                 off += QC * S32 + QW;
@@ -387,7 +367,7 @@ __device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32,
         }
         __builtin_amdgcn_wave_barrier();
     }
-    if (ltid <= m) at(base, ltid) = static_cast<T>(ltid == 0 ? betad : 0.0);
+    if (ltid <= m) *at(base, ltid) = static_cast<T>(ltid == 0 ? betad : 0.0);
 }
 
 // LDS of one lane (bytes): its (TWM+1)^2 corner and one staging block of
@@ -529,7 +509,7 @@ __device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
                 // row k of this step's right task (read by every wave of the lane in
                 // the previous phase) becomes (beta, 0, ..., 0)
                 if (defer_rowk && ltid <= sg.m)
-                    A[sg.k + (int64_t)(sg.p + ltid) * S] = static_cast<T>(ltid == 0 ? beta_row : 0.0);
+                    to_global(A)[sg.k + (int64_t)(sg.p + ltid) * S] = static_cast<T>(ltid == 0 ? beta_row : 0.0);
                 left_task<T, TWM, NTL>(A, S, S32, sg, n, b, corner, stage, scr, ltid);
             }
         }
@@ -537,7 +517,7 @@ __device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();  // every wave of every lane has read its row k
             if (active && (h & 1) == 0 && ltid <= sg.m)
-                A[sg.k + (int64_t)(sg.p + ltid) * S] = static_cast<T>(ltid == 0 ? beta_row : 0.0);
+                to_global(A)[sg.k + (int64_t)(sg.p + ltid) * S] = static_cast<T>(ltid == 0 ? beta_row : 0.0);
         }
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();  // phase complete: its stores are visible inside the workgroup
@@ -692,7 +672,7 @@ __global__ __launch_bounds__(max_threads<TWM>()) void bb_stage_batched(BatchArgs
                 __syncthreads();
                 if (!s_ok) return;
                 ga.stage_prev = nullptr;
-                _Float16* W = reinterpret_cast<_Float16*>(M.W);
+                gptr<_Float16> W = to_global(reinterpret_cast<_Float16*>(M.W));
                 const int64_t count = (int64_t)M.n * (M.S + 1);
                 float mx = 0.f;
                 for (int64_t i = threadIdx.x; i < count; i += blockDim.x) mx = fmaxf(mx, fabsf(static_cast<float>(W[i])));
@@ -702,10 +682,10 @@ __global__ __launch_bounds__(max_threads<TWM>()) void bb_stage_batched(BatchArgs
                 if (threadIdx.x == 0) {
                     float m2 = 0.f;
                     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m2 = fmaxf(m2, s_red[w]);
-                    const int e_old = a.exps[M.exp_off + tk.stage];
+                    const int e_old = to_global(a.exps)[M.exp_off + tk.stage];
                     int e_new = e_old;
                     if (m2 > 0.f && isfinite(m2)) e_new = e_old + (kF16Top - ilogbf(m2));
-                    a.exps[M.exp_off + tk.stage + 1] = e_new;
+                    to_global(a.exps)[M.exp_off + tk.stage + 1] = e_new;
                     s_red[0] = __int_as_float(e_new - e_old);
                 }
                 __syncthreads();
