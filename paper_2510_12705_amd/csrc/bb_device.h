@@ -1,8 +1,7 @@
 // bb_device.h -- device-side building blocks for the gfx950 bulge-chasing kernels.
 //
-// Lane broadcast, the FP64 Householder generator, compensated (Dot2) sums for
-// the reduced-precision storage forms, and the agent-scope dependency
-// primitives used by the persistent kernels.
+// Lane broadcast, the FP64 Householder generator and the TwoSum step of the
+// compensated (Dot2) sums used by the reduced-precision storage forms.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -113,8 +112,9 @@ __device__ __forceinline__ double lapy2(double a, double b) {
     return w * sqrt(1.0 + q * q);
 }
 
-// x_lane: lane t (0 <= t <= m) holds x_t.  Same reflector as house_uniform
-// below, generated through a per-wave LDS scratch `scr` of 2 (TWM + 1) doubles:
+// x_lane: lane t (0 <= t <= m) holds x_t.  On return v[0..TWM] holds the
+// reflector (v[0] = 1, v[t] = 0 for t > m), equal on every lane of the wave,
+// generated through a per-wave LDS scratch `scr` of 2 (TWM + 1) doubles:
 // lane t writes x_t^2 and later x_t / (alpha - beta), every lane reads them back
 // (broadcast reads), so no lane-by-lane register broadcast is needed.  The
 // squares are summed left to right in the same order and operations as the
@@ -175,61 +175,6 @@ __device__ __forceinline__ void house_lds(double x_lane, int m, double* scr, V (
     beta = bt;
 }
 
-// x_lane: lane t (0 <= t <= m) holds x_t.  On return v[0..TWM] holds the
-// reflector (v[0] = 1, v[t] = 0 for t > m), uniform across the wave.  The lane
-// values are re-read with readlane where needed rather than kept in an array,
-// which keeps register pressure low for wide windows.
-template <int TWM, typename V>
-__device__ __forceinline__ void house_uniform(double x_lane, int m, V (&v)[TWM + 1], double& tau, double& beta) {
-    constexpr double tsml = 0x1p-511, tbig = 0x1p486;
-    const double xm = mask_above(x_lane, m);  // lanes above m hold +0
-    double alpha = readlane_f64(xm, 0);
-    // xNRM2 of x2: when every nonzero |x_t| lies in [tsml, tbig] it is the square
-    // root of the plain left-to-right sum of squares (zeros add exactly +0);
-    // otherwise the general algorithm runs over the lanes.
-    bool mid = true;
-    double amed = 0.0;
-#pragma unroll
-    for (int t = 1; t <= TWM; ++t) {
-        const double ax = fabs(readlane_f64(xm, t));
-        mid = mid & ((ax == 0.0) | ((ax >= tsml) & (ax <= tbig)));
-        amed = amed + ax * ax;
-    }
-    double xn = mid ? sqrt(amed) : nrm2_lanes_general(xm, m, 0);
-    v[0] = V(1);
-    if (xn == 0.0) {
-#pragma unroll
-        for (int t = 1; t <= TWM; ++t) v[t] = V(0);
-        tau = 0.0;
-        beta = alpha;
-        return;
-    }
-    double h = lapy2(alpha, xn);
-    double bt = alpha >= 0.0 ? -h : h;
-    constexpr double safmin = 2.2250738585072014e-308 / 2.220446049250313e-16;  // DBL_MIN / DBL_EPSILON
-    constexpr double rsafmn = 1.0 / safmin;
-    int knt = 0;
-    if (fabs(bt) < safmin) {
-        do {
-            ++knt;
-            bt = bt * rsafmn;
-            alpha = alpha * rsafmn;
-        } while (fabs(bt) < safmin && knt < 20);
-        xn = nrm2_lanes_general(xm, m, knt);
-        h = lapy2(alpha, xn);
-        bt = alpha >= 0.0 ? -h : h;
-    }
-    const double scal = 1.0 / (alpha - bt);
-    double xs = xm;  // this lane's x_t, rescaled like the reference (exact powers of two)
-#pragma unroll 1
-    for (int i = 0; i < knt; ++i) xs = xs * rsafmn;
-#pragma unroll
-    for (int t = 1; t <= TWM; ++t) v[t] = static_cast<V>(readlane_f64(xs, t) * scal);  // x_t == 0 for t > m
-    tau = (bt - alpha) / bt;
-    for (int i = 0; i < knt; ++i) bt = bt * safmin;
-    beta = bt;
-}
-
 // ---------------------------------------------------------------------------
 // Dot products: plain FMA chain (FP64) and Ogita-Rump-Oishi Dot2 (FP32).
 // ---------------------------------------------------------------------------
@@ -237,61 +182,6 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
     s = a + b;
     float bb = s - a;
     e = (a - (s - bb)) + (b - bb);
-}
-
-// ---------------------------------------------------------------------------
-// Dependency primitives.  progress[r] counts completed half-steps of sweep r
-// (2j+1 after the right task of step j, 2j+2 after its left task) and becomes
-// kDone when sweep r and every earlier sweep finished.
-// ---------------------------------------------------------------------------
-struct SyncCtx {
-    int* abort_flag;         // device word: set on watchdog expiry, polled by every waiter
-    int* err_word;           // host-mapped word receiving the error code
-    unsigned spin_limit;     // polls before the watchdog fires
-};
-
-// All threads of the block call this; thread 0 polls.  Returns false if the
-// pipeline was aborted (then every thread must leave the kernel).
-__device__ __forceinline__ bool wait_ge(const int* flag, int target, const SyncCtx& s, int* lds_ok) {
-    if (threadIdx.x == 0) {
-        int ok = 1;
-        if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            unsigned spins = 0;
-            while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                __builtin_amdgcn_s_sleep(1);
-                if ((++spins & 255u) == 0) {
-                    if (__hip_atomic_load(s.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                        ok = 0;
-                        break;
-                    }
-                    if (spins > s.spin_limit) {
-                        __hip_atomic_store(s.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        __hip_atomic_store(s.err_word, 2 /*BB_ERR_TIMEOUT*/, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_SYSTEM);
-                        ok = 0;
-                        break;
-                    }
-                }
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        *lds_ok = ok;
-    }
-    __syncthreads();
-    return *lds_ok != 0;
-}
-
-// All threads call this after their last store of a task.  Every wave first
-// drains its own outstanding memory operations (so its stores have reached the
-// L2 of this XCD), the block synchronises, and thread 0 alone then performs the
-// agent-scope release (one L2 write-back for the whole block) and the flag store.
-__device__ __forceinline__ void publish(int* flag, int value) {
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_store(flag, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
 }
 
 }  // namespace bbk

@@ -158,6 +158,24 @@ __device__ __forceinline__ gptr<P> wave_uniform(P* ptr) {
 // a value known to be equal on every lane of the wave, moved to a scalar register
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Band stores are made at agent scope: each is coherent across the device once
+// it is acknowledged, so a workgroup releases its results to another one by
+// waiting for its stores (s_waitcnt) and then storing the progress word -- no
+// write-back of the whole L2, which every agent-scope release fence would do.
+template <typename T>
+__device__ __forceinline__ void st_agent(gptr<T> p, T v) {
+    if constexpr (sizeof(T) == 8) {
+        __hip_atomic_store(reinterpret_cast<gptr<unsigned long long>>(p), __builtin_bit_cast(unsigned long long, v),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else if constexpr (sizeof(T) == 4) {
+        __hip_atomic_store(reinterpret_cast<gptr<unsigned int>>(p), __builtin_bit_cast(unsigned int, v), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        __hip_atomic_store(reinterpret_cast<gptr<unsigned short>>(p), __builtin_bit_cast(unsigned short, v),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ gptr<T> at(gptr<T> base, int off) {
     return reinterpret_cast<gptr<T>>(reinterpret_cast<gptr<char>>(base) + static_cast<uint32_t>(off) * sizeof(T));
@@ -221,7 +239,7 @@ __device__ __forceinline__ void load_row(C (&av)[TWM + 1], gptr<T> base, int S, 
 template <typename T, typename C, int TWM>
 __device__ __forceinline__ void store_row(const C (&av)[TWM + 1], gptr<T> base, int S, int di, int m) {
 #pragma unroll
-    for (int t = TWM; t >= 0; --t) *at(base, di + min(t, m) * S) = static_cast<T>(av[t]);
+    for (int t = TWM; t >= 0; --t) st_agent(at(base, di + min(t, m) * S), static_cast<T>(av[t]));
 }
 
 // ---------------------------------------------------------------------------
@@ -354,7 +372,7 @@ __device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32,
             int off = (1 + c0 + col) * S32 + t;
 #pragma unroll 4
             for (int u = 0; u < LDC; ++u) {
-                if (t <= m && col < cmax) *at(base, off) = static_cast<T>(blk[u * kWave + lane]);
+                if (t <= m && col < cmax) st_agent(at(base, off), static_cast<T>(blk[u * kWave + lane]));
                 col += QC;
                 t += QW;
                 off += QC * S32 + QW;
@@ -367,7 +385,7 @@ __device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32,
         }
         __builtin_amdgcn_wave_barrier();
     }
-    if (ltid <= m) *at(base, ltid) = static_cast<T>(ltid == 0 ? betad : 0.0);
+    if (ltid <= m) st_agent(at(base, ltid), static_cast<T>(ltid == 0 ? betad : 0.0));
 }
 
 // LDS of one lane (bytes): its (TWM+1)^2 corner and one staging block of
@@ -423,10 +441,6 @@ struct GroupArgs {
     int* abort_flag;
     int* err_word;
     unsigned spin_limit;
-    bool next_local;         // the next group runs on this XCD (shares its L2): the release
-                             // only needs this group's stores completed, which every wave
-                             // waits for before the phase barrier; otherwise the release
-                             // also writes this XCD's L2 back (agent scope)
 };
 
 // Executed by the whole workgroup (G lanes of NTL threads).  In phase P lane g
@@ -509,7 +523,7 @@ __device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
                 // row k of this step's right task (read by every wave of the lane in
                 // the previous phase) becomes (beta, 0, ..., 0)
                 if (defer_rowk && ltid <= sg.m)
-                    to_global(A)[sg.k + (int64_t)(sg.p + ltid) * S] = static_cast<T>(ltid == 0 ? beta_row : 0.0);
+                    st_agent(to_global(A) + (sg.k + (int64_t)(sg.p + ltid) * S), static_cast<T>(ltid == 0 ? beta_row : 0.0));
                 left_task<T, TWM, NTL>(A, S, S32, sg, n, b, corner, stage, scr, ltid);
             }
         }
@@ -517,7 +531,7 @@ __device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();  // every wave of every lane has read its row k
             if (active && (h & 1) == 0 && ltid <= sg.m)
-                to_global(A)[sg.k + (int64_t)(sg.p + ltid) * S] = static_cast<T>(ltid == 0 ? beta_row : 0.0);
+                st_agent(to_global(A) + (sg.k + (int64_t)(sg.p + ltid) * S), static_cast<T>(ltid == 0 ? beta_row : 0.0));
         }
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();  // phase complete: its stores are visible inside the workgroup
@@ -526,7 +540,7 @@ __device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
         if (tid == 0) {
             const int done_last = min(max(P + 1 - H * (nl - 1), 0), len_last);
             if (done_last > published) {
-                if (!ga.next_local) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                // every wave waited for its (agent-scope) stores before the barrier
                 __hip_atomic_store(ga.last, done_last, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 published = done_last;
             }
@@ -538,7 +552,6 @@ __device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
         if (ok && ga.prev && known < kDone && poll_ge(ga.prev, kDone, ga.abort_flag, ga.err_word, ga.spin_limit) < 0)
             ok = 0;
         if (ok) {
-            if (!ga.next_local) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __hip_atomic_store(ga.last, kDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         *s_ok = ok;
@@ -607,7 +620,6 @@ __global__ __launch_bounds__(max_threads<TWM>()) void bb_stage(StageArgs a) {
         ga.abort_flag = a.abort_flag;
         ga.err_word = a.err_word;
         ga.spin_limit = a.spin_limit;
-        ga.next_local = a.nxcd > 0 && (q + 1) % Q != 0;
         if (!run_group<T, TWM, NTL>(ga, lds, &s_ok)) return;
     }
 }
@@ -657,7 +669,6 @@ __global__ __launch_bounds__(max_threads<TWM>()) void bb_stage_batched(BatchArgs
             ga.stage_prev = a.progress + Sp.prog_off + Sp.ngroups - 1;
         }
         ga.last = a.progress + St.prog_off + tk.group;
-        ga.next_local = false;
         ga.abort_flag = a.abort_flag;
         ga.err_word = a.err_word;
         ga.spin_limit = a.spin_limit;
@@ -685,14 +696,14 @@ __global__ __launch_bounds__(max_threads<TWM>()) void bb_stage_batched(BatchArgs
                     const int e_old = to_global(a.exps)[M.exp_off + tk.stage];
                     int e_new = e_old;
                     if (m2 > 0.f && isfinite(m2)) e_new = e_old + (kF16Top - ilogbf(m2));
-                    to_global(a.exps)[M.exp_off + tk.stage + 1] = e_new;
+                    st_agent(to_global(a.exps) + (M.exp_off + tk.stage + 1), e_new);
                     s_red[0] = __int_as_float(e_new - e_old);
                 }
                 __syncthreads();
                 const int de = __float_as_int(s_red[0]);
                 if (de != 0)
                     for (int64_t i = threadIdx.x; i < count; i += blockDim.x)
-                        W[i] = static_cast<_Float16>(ldexpf(static_cast<float>(W[i]), de));
+                        st_agent(W + i, static_cast<_Float16>(ldexpf(static_cast<float>(W[i]), de)));
                 __builtin_amdgcn_s_waitcnt(0);
                 __syncthreads();
             }

@@ -32,11 +32,13 @@ int default_threads(int rows, int dtype) {
     return nt;
 }
 
-// sweeps per workgroup: about 256 threads per workgroup (one wave per SIMD of a
-// CU for the widest windows; narrow windows group several sweeps)
+// sweeps per workgroup: one.  Sweeps sharing a workgroup share its CU's SIMDs,
+// so grouping slows every lane more than it saves in hand-over cost once the
+// hand-over stays within an XCD's L2.
 int default_lanes(int threads_per_lane, int dtype) {
+    (void)threads_per_lane;
     (void)dtype;
-    return std::max(1, std::min(16, 256 / threads_per_lane));
+    return 1;
 }
 
 int kernel_twm(int tw) { return tw <= 8 ? 8 : tw <= 16 ? 16 : 32; }

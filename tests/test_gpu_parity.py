@@ -122,6 +122,19 @@ def test_xcd_run_is_bitwise_identical(bb, xcd_run):
     assert np.array_equal(d, do) and np.array_equal(e, eo)
 
 
+@pytest.mark.parametrize("n,b,tw", [(333, 64, 1), (800, 40, 2), (513, 2, 1)])
+@pytest.mark.parametrize("params", [dict(), dict(groups_per_cu=1), dict(xcd_run=2), dict(threads_per_window=256)])
+def test_one_sweep_per_workgroup_bitwise(bb, n, b, tw, params):
+    """One sweep per workgroup hands every sweep over between workgroups, with
+    tiny windows (tw <= 2) the hand-overs are microseconds apart: the results
+    must still be bitwise the oracle's."""
+    _say("case n=%d b=%d tw=%d one sweep per workgroup %s" % (n, b, tw, params))
+    band = inputs.band_normal(n, b, seed=n + b)
+    d, e = gpu_reduce(bb, band, n, b, tw=tw, sweeps_per_group=1, **params)
+    do, eo = oracle.reduce(band, n, b, tw)
+    assert np.array_equal(d, do) and np.array_equal(e, eo)
+
+
 def test_larger_lag_is_bitwise_identical(bb):
     n, b, tw = 1200, 40, 8
     band = inputs.band_normal(n, b, seed=5)
