@@ -370,7 +370,7 @@ __device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32,
             int col = lane / LDC, t = lane - col * LDC;
             const int cmax = cols - c0;
             int off = (1 + c0 + col) * S32 + t;
-#pragma unroll 4
+#pragma unroll 8
             for (int u = 0; u < LDC; ++u) {
                 if (t <= m && col < cmax) st_agent(at(base, off), static_cast<T>(blk[u * kWave + lane]));
                 col += QC;
