@@ -109,6 +109,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=6144)
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the library's timed parameter search for each storage type before timing")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="before the workload, run one device copy of this many MiB (a known-size kernel "
                          "against which HBM byte counters are calibrated)")
@@ -141,8 +143,10 @@ def main():
               file=sys.stderr, flush=True)
         del src, dst
     bb.reset_params()
+    if args.autotune:
+        print("[bench] autotune fp64: %r" % bb.autotune(n, b, bb.F64), file=sys.stderr, flush=True)
     ms64, stage_ms, launches, d, e = time_reductions(bb, torch, band64, n, b, args.steps, args.warmup, "fp64")
-    p = bb.autotune(n, b, bb.F64)  # reports the parameters the call used (no tuning run when cached)
+    p = bb.resolved_params(n, b, bb.F64)  # the parameters the timed calls used
     alg64 = bb.model_bytes(n, b, 8, TW_REF[8])
     per_launch_bytes = alg64 * args.steps / max(launches, 1)
     avg_launch_s = stage_ms / max(launches, 1) / 1e3
@@ -164,7 +168,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "n=%d, b=%d upper band, i.i.d. N(0,1) entries (seed %d), FP64 storage" % (n, b, seed),
                    "n": n, "b": b, "storage": "fp64", "tw": p.tw, "threads_per_window": p.threads_per_window,
-                   "sweeps_per_group": p.sweeps_per_group, "groups_per_cu": p.groups_per_cu,
+                   "sweeps_per_group": p.sweeps_per_group, "groups_per_cu": p.groups_per_cu, "xcd_run": p.xcd_run,
+                   "autotuned": bool(args.autotune),
                    "stages": len(bb.plan(b, p.tw))},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": traffic,
@@ -180,8 +185,10 @@ def main():
     out["us_per_critical_half_step"] = round(ms64 * 1e3 / crit, 4)
     if not args.no_fp32:
         band32 = band64.to(torch.float32)
+        if args.autotune:
+            print("[bench] autotune fp32: %r" % bb.autotune(n, b, bb.F32), file=sys.stderr, flush=True)
         ms32, st32, l32, _, _ = time_reductions(bb, torch, band32, n, b, args.steps, args.warmup, "fp32")
-        p32 = bb.autotune(n, b, bb.F32)
+        p32 = bb.resolved_params(n, b, bb.F32)
         alg32 = bb.model_bytes(n, b, 4, TW_REF[4])
         out["fp32_store"] = {"ms": round(ms32, 3), "tw": p32.tw, "alg_bytes": alg32,
                              "pct_roofline_whole_call": round(100.0 * alg32 / (ms32 / 1e3) / 1e9 / PEAK_HBM_GBPS, 2),

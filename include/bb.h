@@ -125,12 +125,22 @@ int bb_set_params(const bb_params_t *p);
 int bb_get_params(bb_params_t *p);
 
 /*
- * Autotune for one problem shape: candidates are seeded and ranked by a
- * bytes-per-step model, the best few are timed on a synthetic band of this
- * shape on `stream`, and the fastest is cached for (n bucket, b, dtype) and
- * returned in *out (may be NULL).  Synchronises `stream`.
+ * Autotune for one problem shape: a short list of parameter sets (the built-in
+ * defaults and shapes that win in other regimes; fields fixed by bb_set_params
+ * are kept in all of them) is ranked by a critical-path model, the best six are
+ * timed on a synthetic band of this shape (n capped at 32768) on `stream`, and
+ * the fastest is cached for (floor(log2 n), min(b, n-1), dtype).  Later calls of
+ * bb_reduce for that key use the cached fields that bb_set_params leaves at 0.
+ * *out (may be NULL) receives the first-stage launch shape of the winner.
+ * Allocates stream-ordered device memory and synchronises `stream`.
+ * bb_release() clears the cache.
  */
 int bb_autotune(int64_t n, int64_t b, bb_dtype_t dtype, void *stream, bb_params_t *out);
+
+/* The parameters (first-stage launch shape) bb_reduce would use for this shape
+ * now: bb_set_params fields, then an autotuned entry, then the defaults.  Host
+ * only; no device work.  -4 if out is NULL. */
+int bb_resolved_params(int64_t n, int64_t b, bb_dtype_t dtype, bb_params_t *out);
 
 /* Device bytes of working memory one bb_reduce call of this shape allocates. */
 size_t bb_workspace_bytes(int64_t n, int64_t b, bb_dtype_t dtype);

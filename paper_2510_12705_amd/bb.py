@@ -57,6 +57,8 @@ def _load():
     lib.bb_get_params.restype = ctypes.c_int
     lib.bb_autotune.argtypes = [i64, i64, ctypes.c_int, vp, ctypes.POINTER(Params)]
     lib.bb_autotune.restype = ctypes.c_int
+    lib.bb_resolved_params.argtypes = [i64, i64, ctypes.c_int, ctypes.POINTER(Params)]
+    lib.bb_resolved_params.restype = ctypes.c_int
     lib.bb_workspace_bytes.argtypes = [i64, i64, ctypes.c_int]
     lib.bb_workspace_bytes.restype = ctypes.c_size_t
     lib.bb_model_bytes.argtypes = [i64, i64, ctypes.c_int, ctypes.c_int]
@@ -80,7 +82,7 @@ def _load():
 
 lib = _load()
 
-EXPORTS = ("bb_reduce", "bb_reduce_batched", "bb_set_params", "bb_get_params", "bb_autotune",
+EXPORTS = ("bb_reduce", "bb_reduce_batched", "bb_set_params", "bb_get_params", "bb_autotune", "bb_resolved_params",
            "bb_workspace_bytes", "bb_model_bytes", "bb_plan", "bb_min_lag", "bb_stream_status",
            "bb_release", "bb_error_string", "bb_timing_enable", "bb_timing_read")
 
@@ -163,6 +165,13 @@ def get_params() -> Params:
 def autotune(n: int, b: int, dtype: int, stream=None) -> Params:
     p = Params()
     _check(lib.bb_autotune(n, b, dtype, _stream_handle(stream), ctypes.byref(p)), "bb_autotune")
+    return p
+
+
+def resolved_params(n: int, b: int, dtype: int) -> Params:
+    """Launch parameters bb_reduce would use for this shape (no device work)."""
+    p = Params()
+    _check(lib.bb_resolved_params(n, b, dtype, ctypes.byref(p)), "bb_resolved_params")
     return p
 
 

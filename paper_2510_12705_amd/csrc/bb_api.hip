@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cstring>
 #include <mutex>
 #include <vector>
 
@@ -92,23 +93,32 @@ struct Launch {
     size_t lds_limit;
 };
 
-Launch resolve(int64_t n, int64_t b, int dtype, size_t lds_limit = 65536) {
-    bb_params_t p;
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        p = g_params;
-    }
+bb_params_t current_params() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_params;
+}
+
+// Effective launch shape: a nonzero field of `p` wins, then a nonzero field of an
+// autotuned entry for this shape (if use_cache), then the built-in default.
+Launch resolve(int64_t n, int64_t b, int dtype, size_t lds_limit, bb_params_t p, bool use_cache = true) {
     bbp::Tuned t;
-    bool cached = bbp::autotune_lookup(n, b, dtype, &t);
+    if (use_cache && bbp::autotune_lookup(n, b, dtype, &t)) {
+        if (!p.tw) p.tw = t.p.tw;
+        if (!p.threads_per_window) p.threads_per_window = t.p.threads_per_window;
+        if (!p.sweeps_per_group) p.sweeps_per_group = t.p.sweeps_per_group;
+        if (!p.groups_per_cu) p.groups_per_cu = t.p.groups_per_cu;
+        if (!p.lag) p.lag = t.p.lag;
+        if (!p.xcd_run) p.xcd_run = t.p.xcd_run;
+    }
     Launch L;
-    L.tw = p.tw ? p.tw : cached ? t.tw : bbp::default_tw(dtype);
+    L.tw = p.tw ? p.tw : bbp::default_tw(dtype);
     int rows = (int)std::min<int64_t>(b, std::max<int64_t>(n - 1, 1)) + L.tw;
-    L.ntl = p.threads_per_window ? p.threads_per_window : cached ? t.ntl : bbp::default_threads(rows, dtype);
-    L.lanes = p.sweeps_per_group ? p.sweeps_per_group : cached ? t.lanes : bbp::default_lanes(L.ntl, dtype);
-    L.ntl_fixed = p.threads_per_window != 0 || cached;
-    L.lanes_fixed = p.sweeps_per_group != 0 || cached;
+    L.ntl = p.threads_per_window ? p.threads_per_window : bbp::default_threads(rows, dtype);
+    L.lanes = p.sweeps_per_group ? p.sweeps_per_group : bbp::default_lanes(L.ntl, dtype);
+    L.ntl_fixed = p.threads_per_window != 0;
+    L.lanes_fixed = p.sweeps_per_group != 0;
     L.lds_limit = lds_limit;
-    L.groups_per_cu = p.groups_per_cu ? p.groups_per_cu : cached ? t.groups_per_cu : 2;
+    L.groups_per_cu = p.groups_per_cu ? p.groups_per_cu : 2;
     L.lag = p.lag;
     L.xcd_run = p.xcd_run ? p.xcd_run : 8;
     // fit the workgroup's LDS (corners + staging blocks) and thread limits
@@ -367,6 +377,9 @@ void batch_plans_clear() {
 
 extern "C" {
 
+static int reduce_impl(int64_t n, int64_t b, int dtype, const void* band, int64_t ldband, double* d, double* e,
+                       hipStream_t st, DeviceState* ds, const bb_params_t& params, bool use_cache);
+
 int bb_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, int64_t ldband, double* d, double* e,
               void* stream) {
     if (n < 0) return -1;
@@ -378,14 +391,19 @@ int bb_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, int64_t 
     if (n > 1 && !e) return -7;
     if (n > (int64_t)1 << 30) return -1;
     if (n == 0) return BB_OK;
-    hipStream_t st = (hipStream_t)stream;
     DeviceState* ds = nullptr;
     int rc = device_state(&ds);
     if (rc) return rc;
+    return reduce_impl(n, b, dtype, band, ldband, d, e, (hipStream_t)stream, ds, current_params(), true);
+}
 
+// Body of bb_reduce for validated arguments, with explicit parameters.
+static int reduce_impl(int64_t n, int64_t b, int dtype, const void* band, int64_t ldband, double* d, double* e,
+                       hipStream_t st, DeviceState* ds, const bb_params_t& params, bool use_cache) {
+    int rc = BB_OK;
     const int64_t b_in = b;
     const int64_t bb = std::min<int64_t>(b, n - 1);
-    Launch L = resolve(n, bb, dtype, ds->lds_per_block);
+    Launch L = resolve(n, bb, dtype, ds->lds_per_block, params, use_cache);
     if (L.tw < 1 || L.tw > bbp::kMaxTW) return BB_ERR_UNSUPPORTED;
     bbp::Plan plan = bbp::make_plan(bb, L.tw);
     Workspace ws = workspace_layout(n, bb, dtype, L.tw);
@@ -482,7 +500,7 @@ int bb_reduce_batched(int64_t count, const int64_t* n, const int64_t* b, bb_dtyp
         max_n = std::max(max_n, n[i]);
         max_b = std::max(max_b, std::min(b[i], std::max<int64_t>(n[i] - 1, 0)));
     }
-    Launch L = resolve(max_n, max_b, dtype, ds->lds_per_block);
+    Launch L = resolve(max_n, max_b, dtype, ds->lds_per_block, current_params());
     if (L.tw < 1 || L.tw > bbp::kMaxTW) return BB_ERR_UNSUPPORTED;
     BatchPlan* bp = nullptr;
     rc = batch_plan(count, n, b, dtype, L, st, &bp);
@@ -520,7 +538,7 @@ int bb_get_params(bb_params_t* p) {
 size_t bb_workspace_bytes(int64_t n, int64_t b, bb_dtype_t dtype) {
     if (n <= 0 || b < 0) return 0;
     const int64_t bb = std::min<int64_t>(b, n - 1);
-    Launch L = resolve(n, bb, dtype);
+    Launch L = resolve(n, bb, dtype, 65536, current_params());
     return workspace_layout(n, bb, dtype, L.tw).total;
 }
 
@@ -602,14 +620,114 @@ const char* bb_error_string(int code) {
 
 }  // extern "C"
 
+// Critical-path model used to rank autotune candidates: per stage, lag * (n - c)
+// half-steps, each costing a fixed latency plus a term growing with the window.
+static double model_time(int64_t n, int64_t b, int elem, int tw) {
+    double t = 0.0;
+    for (const bbp::Stage& s : bbp::make_plan(b, tw).stages)
+        t += (double)s.lag * (double)(n - s.c) * (1.0 + (double)elem * (s.b + s.tw) * (s.tw + 1) / 16384.0);
+    return t;
+}
+
 extern "C" int bb_autotune(int64_t n, int64_t b, bb_dtype_t dtype, void* stream, bb_params_t* out) {
-    (void)stream;
     if (n < 0) return -1;
     if (b < 0) return -2;
     if (dtype != BB_F64 && dtype != BB_F32 && dtype != BB_F16) return -3;
     DeviceState* ds = nullptr;
+    int rc = device_state(&ds);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t bb = std::min<int64_t>(b, std::max<int64_t>(n - 1, 0));
+    const bb_params_t user = current_params();
+    auto report = [&](const bb_params_t& p) {
+        Launch L = resolve(n, bb, dtype, ds->lds_per_block, p, false);
+        if (out) *out = bb_params_t{L.tw, L.ntl, L.lanes, L.groups_per_cu, L.lag, L.xcd_run};
+    };
+    if (n < 64 || bb <= 1) {  // nothing worth timing
+        report(user);
+        return BB_OK;
+    }
+    // candidates: the built-in defaults and the shapes that win in some regime;
+    // fields fixed by bb_set_params hold for every candidate
+    std::vector<bb_params_t> cands = {{0, 0, 0, 0, 0, 0},   {0, 256, 1, 1, 0, 0}, {0, 0, 0, 1, 0, 0},
+                                      {16, 0, 0, 0, 0, 0},  {0, 0, 2, 0, 0, 0},   {0, 0, 0, 0, 0, 16},
+                                      {0, 128, 1, 2, 0, 0}, {8, 0, 0, 0, 0, 0}};
+    for (bb_params_t& c : cands) {
+        if (user.tw) c.tw = user.tw;
+        if (user.threads_per_window) c.threads_per_window = user.threads_per_window;
+        if (user.sweeps_per_group) c.sweeps_per_group = user.sweeps_per_group;
+        if (user.groups_per_cu) c.groups_per_cu = user.groups_per_cu;
+        if (user.lag) c.lag = user.lag;
+        if (user.xcd_run) c.xcd_run = user.xcd_run;
+    }
+    const int64_t nt = std::min<int64_t>(n, 32768);
+    const int64_t bt = std::min<int64_t>(bb, nt - 1);
+    const int elem = (int)elem_size(dtype);
+    std::vector<std::pair<double, bb_params_t>> ranked;
+    for (const bb_params_t& c : cands) {
+        bool dup = false;
+        for (auto& r : ranked)
+            if (!std::memcmp(&r.second, &c, sizeof(c))) dup = true;
+        if (dup) continue;
+        const int tw = c.tw ? c.tw : bbp::default_tw(dtype);
+        ranked.emplace_back(model_time(nt, bt, elem, std::min<int64_t>(tw, std::max<int64_t>(bt - 1, 1))), c);
+    }
+    std::stable_sort(ranked.begin(), ranked.end(),
+                     [](const std::pair<double, bb_params_t>& x, const std::pair<double, bb_params_t>& y) {
+                         return x.first < y.first * 0.999;
+                     });
+    if (ranked.size() > 6) ranked.resize(6);
+    // synthetic band of the (capped) shape, timed on `stream`
+    void *band = nullptr, *dbuf = nullptr;
+    const size_t band_bytes = (size_t)nt * (size_t)(bt + 1) * (size_t)elem;
+    if (hipMallocAsync(&band, band_bytes, st) != hipSuccess) return BB_ERR_NOMEM;
+    if (hipMallocAsync(&dbuf, sizeof(double) * 2 * (size_t)nt, st) != hipSuccess) {
+        (void)hipFreeAsync(band, st);
+        return BB_ERR_NOMEM;
+    }
+    double* d = static_cast<double*>(dbuf);
+    double* e = d + nt;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    rc = check_hip(bbk::launch_fill_synth(dtype, band, (int64_t)(band_bytes / elem), 0x5eed, st));
+    if (!rc) rc = check_hip(hipEventCreate(&e0));
+    if (!rc) rc = check_hip(hipEventCreate(&e1));
+    bb_params_t best = ranked.front().second;
+    float best_ms = 1e30f;
+    // one untimed run warms the memory pool and the code, then one timed run each
+    if (!rc) rc = reduce_impl(nt, bt, dtype, band, bt + 1, d, e, st, ds, ranked.front().second, false);
+    for (size_t i = 0; i < ranked.size() && !rc; ++i) {
+        const bb_params_t& c = ranked[i].second;
+        rc = check_hip(hipEventRecord(e0, st));
+        if (!rc) rc = reduce_impl(nt, bt, dtype, band, bt + 1, d, e, st, ds, c, false);
+        if (!rc) rc = check_hip(hipEventRecord(e1, st));
+        if (!rc) rc = check_hip(hipEventSynchronize(e1));
+        float ms = 0.f;
+        if (!rc) rc = check_hip(hipEventElapsedTime(&ms, e0, e1));
+        if (!rc && __atomic_load_n(ds->err_host, __ATOMIC_SEQ_CST)) rc = BB_ERR_TIMEOUT;
+        if (!rc && ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFreeAsync(dbuf, st);
+    (void)hipFreeAsync(band, st);
+    if (hipStreamSynchronize(st) != hipSuccess && !rc) rc = BB_ERR_HIP;
+    if (rc) return rc;
+    bbp::autotune_store(n, bb, dtype, bbp::Tuned{best});
+    report(best);
+    return BB_OK;
+}
+
+extern "C" int bb_resolved_params(int64_t n, int64_t b, bb_dtype_t dtype, bb_params_t* out) {
+    if (n < 0) return -1;
+    if (b < 0) return -2;
+    if (dtype != BB_F64 && dtype != BB_F32 && dtype != BB_F16) return -3;
+    if (!out) return -4;
+    DeviceState* ds = nullptr;
     const size_t lds = device_state(&ds) == BB_OK ? ds->lds_per_block : 65536;
-    Launch L = resolve(n, std::min<int64_t>(b, std::max<int64_t>(n - 1, 0)), dtype, lds);
-    if (out) *out = bb_params_t{L.tw, L.ntl, L.lanes, L.groups_per_cu, L.lag, L.xcd_run};
+    Launch L = resolve(n, std::min<int64_t>(b, std::max<int64_t>(n - 1, 0)), dtype, lds, current_params());
+    *out = bb_params_t{L.tw, L.ntl, L.lanes, L.groups_per_cu, L.lag, L.xcd_run};
     return BB_OK;
 }

@@ -66,6 +66,8 @@ hipError_t launch_pack(int dtype, const void* band, int64_t ldband, int64_t n, i
 hipError_t launch_extract(int dtype, const void* W, int64_t n, int64_t ldw, int64_t uo, double inv_scale, double* d,
                           double* e, hipStream_t st);
 hipError_t launch_fill(int* p, int64_t count, int value, hipStream_t st);
+// count elements of the storage type, uniform in [-1, 1) from a hash of (index, seed)
+hipError_t launch_fill_synth(int dtype, void* p, int64_t count, uint64_t seed, hipStream_t st);
 // FP16 storage: reset amax, reduce max|W|, rescale W by a power of two (exps[s] -> exps[s+1]).
 hipError_t launch_f16_rescale(void* W, int64_t count, unsigned* amax, int* exps, int s, hipStream_t st);
 hipError_t launch_extract_f16(const void* W, int64_t n, int64_t ldw, int64_t uo, const int* exps, int nexp,

@@ -128,6 +128,20 @@ __global__ void bb_extract_f16(const _Float16* __restrict__ W, int64_t n, int64_
     }
 }
 
+// Synthetic band for timing (autotuner): entries uniform in [-1, 1) from a hash of
+// the index (splitmix64 finaliser); the values only need to be generic.
+template <typename T>
+__global__ void bb_fill_synth(T* __restrict__ p, int64_t count, uint64_t seed) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t z = (uint64_t)i + seed * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        const double u = (double)(z >> 11) * 0x1p-53;  // [0, 1)
+        p[i] = static_cast<T>(2.0 * u - 1.0);
+    }
+}
+
 __global__ void bb_fill_i32(int* __restrict__ p, int64_t count, int value) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = value;
@@ -809,6 +823,17 @@ hipError_t launch_extract_f16(const void* W, int64_t n, int64_t ldw, int64_t uo,
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(bb_extract_f16, dim3(grid), dim3(256), 0, st, static_cast<const _Float16*>(W), n, ldw, uo,
                        exps, nexp, d, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_synth(int dtype, void* p, int64_t count, uint64_t seed, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>((count + 255) / 256, 4096);
+    switch (dtype) {
+        case 0: hipLaunchKernelGGL(bb_fill_synth<double>, dim3(grid), dim3(256), 0, st, static_cast<double*>(p), count, seed); break;
+        case 1: hipLaunchKernelGGL(bb_fill_synth<float>, dim3(grid), dim3(256), 0, st, static_cast<float*>(p), count, seed); break;
+        default: hipLaunchKernelGGL(bb_fill_synth<_Float16>, dim3(grid), dim3(256), 0, st, static_cast<_Float16*>(p), count, seed); break;
+    }
     return hipGetLastError();
 }
 

@@ -7,6 +7,8 @@
 
 #include <vector>
 
+#include "bb.h"
+
 namespace bbp {
 
 constexpr int kMaxTW = 32;
@@ -36,8 +38,9 @@ int kernel_twm(int tw);
 // Read + write bytes of the L-shaped window of every step, summed.
 double model_bytes(int64_t n, int64_t b, int elem, int tw);
 
+// autotuned parameters per (n bucket, b, dtype); 0 fields mean automatic
 struct Tuned {
-    int tw, ntl, lanes, groups_per_cu;
+    bb_params_t p;
 };
 bool autotune_lookup(int64_t n, int64_t b, int dtype, Tuned* out);
 void autotune_store(int64_t n, int64_t b, int dtype, const Tuned& t);

@@ -135,6 +135,29 @@ def test_one_sweep_per_workgroup_bitwise(bb, n, b, tw, params):
     assert np.array_equal(d, do) and np.array_equal(e, eo)
 
 
+def test_autotune_caches_a_winner_and_results_stay_bitwise(bb):
+    """The timed search returns a valid launch shape, bb_reduce then uses the
+    cached entry, and the result is still the oracle's bit for bit."""
+    n, b = 2048, 64
+    _say("case autotune n=%d b=%d" % (n, b))
+    bb.release()
+    bb.reset_params()
+    bb.set_params(tw=16)
+    p = bb.autotune(n, b, bb.F64)
+    assert p.tw == 16 and p.threads_per_window in (64, 128, 256) and p.sweeps_per_group >= 1
+    q = bb.resolved_params(n, b, bb.F64)
+    assert (q.tw, q.threads_per_window, q.sweeps_per_group, q.groups_per_cu) == \
+        (p.tw, p.threads_per_window, p.sweeps_per_group, p.groups_per_cu)
+    band = inputs.band_normal(n, b, seed=77)
+    t = torch.from_numpy(band).cuda()
+    d, e = bb.bb_reduce(t, n, b)
+    assert bb.stream_status() == 0
+    do, eo = oracle.reduce(band, n, b, 16)
+    assert np.array_equal(d.cpu().numpy(), do) and np.array_equal(e.cpu().numpy(), eo)
+    bb.release()
+    bb.reset_params()
+
+
 def test_larger_lag_is_bitwise_identical(bb):
     n, b, tw = 1200, 40, 8
     band = inputs.band_normal(n, b, seed=5)
