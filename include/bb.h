@@ -64,6 +64,9 @@ enum {
  *   sweeps_per_group   consecutive sweeps one workgroup advances in lock-step
  *                      (1..16, threads_per_window * sweeps_per_group <= 1024);
  *                      hand-over inside a group costs one workgroup barrier.
+ *                      A stage whose kernel variant accepts fewer threads per
+ *                      workgroup (256 for tw 17..32, 512 for 9..16) runs fewer
+ *                      sweeps per group; results do not depend on it.
  *   groups_per_cu      persistent workgroups launched per compute unit (1..16);
  *                      with sweeps_per_group it caps the sweeps in flight, the
  *                      paper's "Max blocks".

@@ -169,6 +169,12 @@ Workspace workspace_layout(int64_t n, int64_t b, int dtype, int tw) {
 
 int check_hip(hipError_t e) { return e == hipSuccess ? BB_OK : BB_ERR_HIP; }
 
+// The stage kernels address a window with 32-bit byte offsets from a wave-uniform
+// base; the largest spans kWave + TW + 2 band columns.  True when they fit.
+bool window_offsets_fit(const Workspace& w, int dtype) {
+    return (int64_t)(64 + bbp::kMaxTW + 2) * w.ldw * (int64_t)elem_size(dtype) < ((int64_t)1 << 32);
+}
+
 // ---------------------------------------------------------------------------
 // Ragged batch plan, cached per (shapes, dtype, launch parameters, stream): the
 // device workspace is allocated once with hipMalloc and reused, so repeated
@@ -213,6 +219,11 @@ int batch_plan(int64_t count, const int64_t* n, const int64_t* b, int dtype, con
                 *out = p;
                 return BB_OK;
             }
+    }
+    for (int64_t i = 0; i < count; ++i) {
+        const int64_t bb = n[i] > 0 ? std::min<int64_t>(b[i], n[i] - 1) : 0;
+        if (!window_offsets_fit(workspace_layout(std::max<int64_t>(n[i], 1), bb, dtype, L.tw), dtype))
+            return BB_ERR_UNSUPPORTED;
     }
     BatchPlan* P = new BatchPlan();
     P->key = key;
@@ -407,6 +418,7 @@ static int reduce_impl(int64_t n, int64_t b, int dtype, const void* band, int64_
     if (L.tw < 1 || L.tw > bbp::kMaxTW) return BB_ERR_UNSUPPORTED;
     bbp::Plan plan = bbp::make_plan(bb, L.tw);
     Workspace ws = workspace_layout(n, bb, dtype, L.tw);
+    if (!window_offsets_fit(ws, dtype)) return BB_ERR_UNSUPPORTED;
 
     void* base = nullptr;
     if (hipMallocAsync(&base, ws.total, st) != hipSuccess) return BB_ERR_NOMEM;

@@ -190,9 +190,57 @@ __device__ __forceinline__ void st_agent(gptr<T> p, T v) {
     }
 }
 
+// base + off elements with a 32-bit byte offset, so that a wave-uniform base in
+// scalar registers and one 32-bit offset per lane address the access (the host
+// keeps every in-window byte offset below 2^32).
 template <typename T>
 __device__ __forceinline__ gptr<T> at(gptr<T> base, int off) {
-    return reinterpret_cast<gptr<T>>(reinterpret_cast<gptr<char>>(base) + static_cast<uint32_t>(off) * sizeof(T));
+    return reinterpret_cast<gptr<T>>(reinterpret_cast<gptr<char>>(base) +
+                                     static_cast<uint32_t>(off) * static_cast<uint32_t>(sizeof(T)));
+}
+
+// Window accesses of the two tasks go through raw buffer instructions: the
+// descriptor holds the wave-uniform window base (scalar registers), each lane
+// adds one 32-bit offset and a wave-uniform stride rides in the scalar offset,
+// so a whole row or column segment needs one address register.  Offsets are in
+// elements; the host keeps every in-window byte offset below 2^32, inside the
+// descriptor's range.  Stores carry the agent-scope coherence bit (sc1), the
+// same cache policy as st_agent.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr int kBufDword3 = 0x00020000;  // gfx9 raw buffer: 32-bit data format, no swizzle
+constexpr int kCpolSc1 = 16;            // cache-policy operand: sc1
+
+template <typename T>
+__device__ __forceinline__ Rsrc make_rsrc(gptr<T> base) {
+    void* generic = reinterpret_cast<void*>(__builtin_bit_cast(uint64_t, base));
+    return __builtin_amdgcn_make_buffer_rsrc(generic, (short)0, -1, kBufDword3);
+}
+
+template <typename T>
+__device__ __forceinline__ T buf_ld(Rsrc r, int voff, int soff) {
+    const int vb = (int)(static_cast<uint32_t>(voff) * static_cast<uint32_t>(sizeof(T)));
+    const int sb = (int)(static_cast<uint32_t>(soff) * static_cast<uint32_t>(sizeof(T)));
+    if constexpr (sizeof(T) == 8) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, vb, sb, 0));
+    } else if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, vb, sb, 0));
+    } else {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, vb, sb, 0));
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void buf_st(Rsrc r, int voff, int soff, T v) {
+    const int vb = (int)(static_cast<uint32_t>(voff) * static_cast<uint32_t>(sizeof(T)));
+    const int sb = (int)(static_cast<uint32_t>(soff) * static_cast<uint32_t>(sizeof(T)));
+    if constexpr (sizeof(T) == 8) {
+        using V2 = __attribute__((ext_vector_type(2))) unsigned int;
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, vb, sb, kCpolSc1);
+    } else if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, vb, sb, kCpolSc1);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, vb, sb, kCpolSc1);
+    }
 }
 
 
@@ -238,11 +286,11 @@ __device__ __forceinline__ void apply_segment(C (&av)[TWM + 1], const C (&vs)[TW
 // ---------------------------------------------------------------------------
 // `base` points at A(k, p) of the current step; in-window offsets fit in 32 bits.
 template <typename T, typename C, int TWM>
-__device__ __forceinline__ void load_row(C (&av)[TWM + 1], gptr<T> base, int S, int di, int m) {
+__device__ __forceinline__ void load_row(C (&av)[TWM + 1], Rsrc base, int S, int di, int m) {
     // A(k + di, p + t) = base[di + t * S]
 #pragma unroll
     for (int t = 0; t <= TWM; ++t) {
-        const C v = to_c(*at(base, di + min(t, m) * S));
+        const C v = to_c(buf_ld<T>(base, di, min(t, m) * S));
         av[t] = t <= m ? v : C(0);
     }
 }
@@ -251,9 +299,9 @@ __device__ __forceinline__ void load_row(C (&av)[TWM + 1], gptr<T> base, int S, 
 // clamped address of entry m first and is then overwritten by entry m itself
 // (stores of one thread to one address keep program order).
 template <typename T, typename C, int TWM>
-__device__ __forceinline__ void store_row(const C (&av)[TWM + 1], gptr<T> base, int S, int di, int m) {
+__device__ __forceinline__ void store_row(const C (&av)[TWM + 1], Rsrc base, int S, int di, int m) {
 #pragma unroll
-    for (int t = TWM; t >= 0; --t) st_agent(at(base, di + min(t, m) * S), static_cast<T>(av[t]));
+    for (int t = TWM; t >= 0; --t) buf_st<T>(base, di, min(t, m) * S, static_cast<T>(av[t]));
 }
 
 // ---------------------------------------------------------------------------
@@ -304,8 +352,8 @@ __device__ __forceinline__ double right_task(T* __restrict__ A, int64_t S, int S
     const int k = uni(g.k), p = uni(g.p), m = uni(g.m);  // a wave never spans two sweeps
     const int lane = ltid & (kWave - 1);
     const int rows = p + m - k;  // rows k+1 .. p+m
-    gptr<T> base = wave_uniform(A + k + (int64_t)p * S);  // A(k, p)
-    const double xl = static_cast<double>(*at(base, min(lane, m) * S32));
+    const Rsrc base = make_rsrc(wave_uniform(A + k + (int64_t)p * S));  // A(k, p)
+    const double xl = static_cast<double>(buf_ld<T>(base, min(lane, m) * S32, 0));
     int ri = ltid;
     C av[TWM + 1];
     load_row<T, C, TWM>(av, base, S32, 1 + min(ri, rows - 1), m);
@@ -347,26 +395,33 @@ __device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32,
     const int lane = ltid & (kWave - 1);
     const int wv = ltid / kWave;
     const int cols = min(p + m + b, n - 1) - p;  // columns p+1 .. L
-    gptr<T> base = wave_uniform(A + p + (int64_t)p * S);  // A(p, p); column p+1+ci starts at base + (1 + ci) * S
+    const gptr<T> colp = to_global(A + p + (int64_t)p * S);  // A(p, p), column p
     C* blk = stage + wv * (kWave * LDC);
     const double xl = static_cast<double>(corner[min(lane, m) * LDC]);
     C av[TWM + 1];
-    // column ci of this thread: global rows (clamped to the window), or the corner
-    auto load_cols = [&](int ci) {
-        const int cg = min(max(ci, m), cols - 1);  // an in-window column for every lane
-        const gptr<T> col = at(base, (1 + cg) * S32);
+    // Column ci of this thread: global rows (clamped to the window), or the corner.
+    // The wave's block of columns c0 .. c0+63 is addressed from its first column
+    // (cbase = A(p, p+1+c0)), so the per-lane offsets stay small.
+    auto block_base = [&](int c0) { return make_rsrc(wave_uniform(colp + (int64_t)(1 + c0) * S)); };
+    auto load_cols = [&](Rsrc cbase, int c0, int ci) {
+        const int cg = min(max(ci, m), cols - 1);  // an in-window column for every lane, >= c0
+        const int o = (cg - c0) * S32;
 #pragma unroll
-        for (int t = 0; t <= TWM; ++t) av[t] = to_c(col[min(t, m)]);
+        for (int t = 0; t <= TWM; ++t) av[t] = to_c(buf_ld<T>(cbase, o, min(t, m)));
     };
     int ci = wv * kWave + lane;
     const int c_first = wv * kWave;
-    if (c_first < cols) load_cols(ci);
+    Rsrc cbase = block_base(c_first);
+    if (c_first < cols) load_cols(cbase, c_first, ci);
     C vs[TWM + 1];
     double taud, betad;
     house_lds<TWM>(xl, m, scr, vs, taud, betad);
     const C tau = static_cast<C>(taud);
     for (int c0 = c_first; c0 < cols; c0 += NTL, ci += NTL) {
-        if (c0 != c_first) load_cols(ci);
+        if (c0 != c_first) {
+            cbase = block_base(c0);
+            load_cols(cbase, c0, ci);
+        }
         if (ci < m) {
 #pragma unroll
             for (int t = 0; t <= TWM; ++t) av[t] = corner[t * LDC + ci + 1];
@@ -377,29 +432,27 @@ __device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32,
 #pragma unroll
         for (int t = 0; t <= TWM; ++t) blk[lane * LDC + t] = av[t];
         __builtin_amdgcn_wave_barrier();
-        // write back: slot e = u*kWave + lane holds column col, row t (pitch LDC);
-        // offsets advance incrementally (no multiplies)
+        // Write back.  Store u covers rows 0..TWM-1 of kWave/TWM whole columns
+        // (lane -> column u*CPI + lane/TWM, row lane%TWM): contiguous runs, and a
+        // per-lane offset that is fixed plus a wave-uniform stride.  Row TWM of all
+        // kWave columns follows in one more store.  Every LDS slot is read before
+        // the stores, so they issue back to back.
         {
-            constexpr int QC = kWave / LDC, QW = kWave % LDC;
-            int col = lane / LDC, t = lane - col * LDC;
+            constexpr int CPI = kWave / TWM;
+            const int sub = lane / TWM, t = lane % TWM;
             const int cmax = cols - c0;
-            int off = (1 + c0 + col) * S32 + t;
-#pragma unroll 8
-            for (int u = 0; u < LDC; ++u) {
-                if (t <= m && col < cmax) st_agent(at(base, off), static_cast<T>(blk[u * kWave + lane]));
-                col += QC;
-                t += QW;
-                off += QC * S32 + QW;
-                if (t >= LDC) {
-                    t -= LDC;
-                    ++col;
-                    off += S32 - LDC;
-                }
-            }
+#pragma unroll
+            for (int u = 0; u < TWM; ++u) av[u] = blk[(u * CPI + sub) * LDC + t];
+            av[TWM] = blk[lane * LDC + TWM];
+            const int o = sub * S32 + t;
+#pragma unroll
+            for (int u = 0; u < TWM; ++u)
+                if (t <= m && u * CPI + sub < cmax) buf_st<T>(cbase, o, u * CPI * S32, static_cast<T>(av[u]));
+            if (m == TWM && lane < cmax) buf_st<T>(cbase, lane * S32, TWM, static_cast<T>(av[TWM]));
         }
         __builtin_amdgcn_wave_barrier();
     }
-    if (ltid <= m) st_agent(at(base, ltid), static_cast<T>(ltid == 0 ? betad : 0.0));
+    if (ltid <= m) buf_st<T>(make_rsrc(wave_uniform(colp)), ltid, 0, static_cast<T>(ltid == 0 ? betad : 0.0));
 }
 
 // LDS of one lane (bytes): its (TWM+1)^2 corner and one staging block of
@@ -416,9 +469,12 @@ struct LaneLds {
     static constexpr size_t bytes = lds_align(scratch + scratch_per_wave * (NTL / kWave));
 };
 
-// largest workgroup a variant is compiled for (wider windows need more registers)
+// Largest workgroup a variant is compiled for.  Wider windows need more
+// registers: at 256 threads (one wave per SIMD) the TW <= 32 variant may use more
+// than 256 registers per lane, so the compiler keeps its overflow in the
+// accumulation registers instead of spilling to scratch memory.
 template <int TWM>
-constexpr int max_threads() { return TWM >= 16 ? 512 : 1024; }
+constexpr int max_threads() { return TWM >= 32 ? 256 : (TWM >= 16 ? 512 : 1024); }
 
 // Thread 0 only: spin until *flag >= need (or abort / watchdog).  Returns the value
 // seen (>= need) or -1 on abort; ends with an agent-scope acquire (invalidates this
@@ -499,10 +555,14 @@ __device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
     // (the first phase's barrier publishes *s_ok)
 
     // Row k of a right task is rewritten in the lane's next phase (its left task)
-    // when c >= 2: no half-step that the lag rule lets run before that phase ends
-    // touches those entries.  With c = 1 some do, so the row is written after an
-    // extra barrier in the same phase.
-    const bool defer_rowk = c >= 2;
+    // when no half-step that the lag rule lets run before that phase ends touches
+    // those entries.  An exhaustive happens-before check of the rule (every pair of
+    // half-steps of a stage that it leaves unordered must be disjoint; sweep r-i is
+    // then only known to have completed h + i (H - 1) + 1 half-steps) shows this
+    // for c = 2 and c >= 4; for c = 1 and c = 3 a half-step of a sweep three behind
+    // can reach row k, so there the row is written after an extra barrier in the
+    // same phase.
+    const bool defer_rowk = c == 2 || c >= 4;
     double beta_row = 0.0;
     for (int P = 0; P < P_end; ++P) {
         // ---- dependency on the previous group (thread 0 polls, then acquires) ----
@@ -945,7 +1005,7 @@ hipError_t launch_extract_batched(int dtype, const BatchMatrix* mats, int count,
     }
 }
 
-int stage_max_threads(int twm) { return twm >= 16 ? max_threads<16>() : max_threads<8>(); }
+int stage_max_threads(int twm) { return twm >= 32 ? max_threads<32>() : twm >= 16 ? max_threads<16>() : max_threads<8>(); }
 
 size_t stage_lds_bytes(int dtype, int twm, int ntl, int lanes) {
     // same layout as LaneLds<C, TWM, NTL>

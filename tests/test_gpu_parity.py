@@ -97,6 +97,18 @@ def test_thread_and_lane_counts_are_bitwise_identical(bb, ntl, lanes):
     assert np.array_equal(d, ref[0]) and np.array_equal(e, ref[1])
 
 
+@pytest.mark.parametrize("ntl,lanes", [(64, 4), (128, 2), (256, 1), (256, 4)])
+def test_tw32_group_shapes_are_bitwise_identical(bb, ntl, lanes):
+    """The widest kernel variant (tw 17..32) takes at most 256 threads per workgroup;
+    larger requested groups are reduced by the host, never changing a bit."""
+    n, b, tw = 900, 80, 32
+    band = inputs.band_normal(n, b, seed=6)
+    ref = gpu_reduce(bb, band, n, b, tw=tw, threads_per_window=256, sweeps_per_group=1)
+    d, e = gpu_reduce(bb, band, n, b, tw=tw, threads_per_window=ntl, sweeps_per_group=lanes)
+    assert np.array_equal(d, ref[0]) and np.array_equal(e, ref[1])
+    check_fp64(band, n, b, tw, d, e)
+
+
 @pytest.mark.parametrize("gpc,lanes", [(1, 1), (2, 3), (16, 2), (1, 8)])
 def test_schedule_independence_bitwise(bb, gpc, lanes):
     """Race detector: concurrently running tasks are disjoint, so how many sweeps are in
