@@ -445,10 +445,20 @@ __device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32,
             for (int u = 0; u < TWM; ++u) av[u] = blk[(u * CPI + sub) * LDC + t];
             av[TWM] = blk[lane * LDC + TWM];
             const int o = sub * S32 + t;
+            // the stride is made opaque here so that the per-store offsets are formed
+            // at the stores instead of being kept live in scalar registers across phases
+            int step = CPI * S32;
+            asm volatile("" : "+s"(step));
+            if (m == TWM && cmax >= kWave) {  // whole block: no per-store predicate
 #pragma unroll
-            for (int u = 0; u < TWM; ++u)
-                if (t <= m && u * CPI + sub < cmax) buf_st<T>(cbase, o, u * CPI * S32, static_cast<T>(av[u]));
-            if (m == TWM && lane < cmax) buf_st<T>(cbase, lane * S32, TWM, static_cast<T>(av[TWM]));
+                for (int u = 0; u < TWM; ++u) buf_st<T>(cbase, o, u * step, static_cast<T>(av[u]));
+                buf_st<T>(cbase, lane * S32, TWM, static_cast<T>(av[TWM]));
+            } else {
+#pragma unroll
+                for (int u = 0; u < TWM; ++u)
+                    if (t <= m && u * CPI + sub < cmax) buf_st<T>(cbase, o, u * step, static_cast<T>(av[u]));
+                if (m == TWM && lane < cmax) buf_st<T>(cbase, lane * S32, TWM, static_cast<T>(av[TWM]));
+            }
         }
         __builtin_amdgcn_wave_barrier();
     }
