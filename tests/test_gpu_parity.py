@@ -404,3 +404,38 @@ def test_batched_graph_capture_replays(bb):
         for x, re_ in zip(es, ref_e):
             assert np.array_equal(x[: len(re_)].cpu().numpy(), re_)
         _ = torch.ones(1000, device="cuda").sum().item()   # eager work between replays
+
+
+_WATCHDOG_CHILD = r"""
+import sys
+sys.path.insert(0, sys.argv[1])
+import numpy as np, torch
+from paper_2510_12705_amd import bb, inputs
+n, b = 4096, 64
+band = torch.from_numpy(inputs.band_normal(n, b, seed=11)).cuda()
+d = torch.empty(n, dtype=torch.float64, device="cuda")
+e = torch.empty(n, dtype=torch.float64, device="cuda")
+rc = bb.lib.bb_reduce(n, b, bb.F64, band.data_ptr(), b + 1, d.data_ptr(), e.data_ptr(), None)
+st = bb.lib.bb_stream_status(None)
+print("RESULT", rc, st, flush=True)
+"""
+
+
+def test_watchdog_turns_stalled_waits_into_timeout_error(tmp_path):
+    """A spin limit of one makes every dependency wait give up after its first check:
+    the pipeline must drain (every workgroup exits through the abort word) and the
+    call must report BB_ERR_TIMEOUT (or success if no wait lasted that long)."""
+    import os
+    import subprocess
+    import sys
+    _say("case watchdog with BB_SPIN_LIMIT=1")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    script = tmp_path / "child.py"
+    script.write_text(_WATCHDOG_CHILD)
+    env = dict(os.environ, BB_SPIN_LIMIT="1")
+    r = subprocess.run([sys.executable, str(script), root], env=env, capture_output=True, text=True, timeout=110)
+    assert r.returncode == 0, r.stderr[-2000:]
+    line = [x for x in r.stdout.splitlines() if x.startswith("RESULT")][-1]
+    _, rc, st = line.split()
+    assert int(rc) == 0
+    assert int(st) in (0, 2), st
