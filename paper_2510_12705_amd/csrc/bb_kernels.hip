@@ -344,9 +344,15 @@ __device__ __forceinline__ int sweep_halfsteps(int n, int b, int c, int r) { ret
 // columns p..p+m.  Rows p..p+m (the bottom (m+1)^2 corner) go to the lane's LDS
 // corner for the left task; row k itself is rewritten by the caller after the
 // phase barrier (every wave of the lane has read it by then).  Returns beta.
-template <typename T, int TWM, int NTL>
+// With `split`, the caller has only waited for the weaker condition (see
+// run_group): rows up to p-2 (row k among them) are final then, so they are
+// loaded and the reflector is generated before wait_b() (a workgroup barrier,
+// called by every thread) establishes the full condition for the other rows and
+// for every store.  wait_b() returns false if the pipeline was aborted.
+template <typename T, int TWM, int NTL, typename WaitB>
 __device__ __forceinline__ double right_task(T* __restrict__ A, int64_t S, int S32, StepGeom g,
-                                             typename Compute<T>::type* corner, double* scr, int ltid) {
+                                             typename Compute<T>::type* corner, double* scr, int ltid,
+                                             bool split, WaitB&& wait_b) {
     using C = typename Compute<T>::type;
     constexpr int LDC = TWM + 1;
     const int k = uni(g.k), p = uni(g.p), m = uni(g.m);  // a wave never spans two sweeps
@@ -356,10 +362,13 @@ __device__ __forceinline__ double right_task(T* __restrict__ A, int64_t S, int S
     const double xl = static_cast<double>(buf_ld<T>(base, min(lane, m) * S32, 0));
     int ri = ltid;
     C av[TWM + 1];
-    load_row<T, C, TWM>(av, base, S32, 1 + min(ri, rows - 1), m);
+    const bool early = !split || ri < p - 2 - k;  // row k+1+ri <= p-2
+    if (early) load_row<T, C, TWM>(av, base, S32, 1 + min(ri, rows - 1), m);
     C vs[TWM + 1];
     double taud, betad;
     house_lds<TWM>(xl, m, scr, vs, taud, betad);
+    if (!wait_b()) return betad;
+    if (!early) load_row<T, C, TWM>(av, base, S32, 1 + min(ri, rows - 1), m);
     const C tau = static_cast<C>(taud);
     while (ri < rows) {
         const int i = k + 1 + ri;
@@ -378,6 +387,9 @@ __device__ __forceinline__ double right_task(T* __restrict__ A, int64_t S, int S
 
 // Left task of one lane: reflector from A[p..p+m, p] (held in the corner), applied
 // to rows p..p+m of columns p+1..L; writes column p as (beta, 0, ..., 0).
+// With `split` (see right_task), columns up to p+b-2 are final under the weaker
+// condition: they are loaded, and the reflector (from the corner) generated,
+// before wait_b(); the other columns are loaded after it.
 // Thread ci of the lane owns column p+1+ci (ci += NTL): its m+1 rows are
 // contiguous in memory, so it loads them directly (one base address, immediate
 // offsets; columns p+1..p+m come from the corner block instead).  The loads are in
@@ -385,10 +397,11 @@ __device__ __forceinline__ double right_task(T* __restrict__ A, int64_t S, int S
 // wave's LDS block (column-major, pitch TWM+1) and are written back as contiguous
 // runs across the wave, so the stores are coalesced.  A wave exchanges data only
 // with itself through its block (no barrier).
-template <typename T, int TWM, int NTL>
+template <typename T, int TWM, int NTL, typename WaitB>
 __device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32, StepGeom g, int n, int b,
                                           const typename Compute<T>::type* corner,
-                                          typename Compute<T>::type* stage, double* scr, int ltid) {
+                                          typename Compute<T>::type* stage, double* scr, int ltid,
+                                          bool split, WaitB&& wait_b) {
     using C = typename Compute<T>::type;
     constexpr int LDC = TWM + 1;
     const int p = uni(g.p), m = uni(g.m);  // a wave never spans two sweeps
@@ -412,10 +425,14 @@ __device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32,
     int ci = wv * kWave + lane;
     const int c_first = wv * kWave;
     Rsrc cbase = block_base(c_first);
-    if (c_first < cols) load_cols(cbase, c_first, ci);
+    // column p+1+ci <= p+b-2, or outside the window (its values are discarded)
+    const bool early = !split || ci <= b - 3 || ci >= cols;
+    if (c_first < cols && early) load_cols(cbase, c_first, ci);
     C vs[TWM + 1];
     double taud, betad;
     house_lds<TWM>(xl, m, scr, vs, taud, betad);
+    if (!wait_b()) return;
+    if (c_first < cols && !early) load_cols(cbase, c_first, ci);
     const C tau = static_cast<C>(taud);
     for (int c0 = c_first; c0 < cols; c0 += NTL, ci += NTL) {
         if (c0 != c_first) {
@@ -573,9 +590,18 @@ __device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
     // can reach row k, so there the row is written after an extra barrier in the
     // same phase.
     const bool defer_rowk = c == 2 || c >= 4;
+    // With one sweep per workgroup the wait of a phase is split in two.  Once the
+    // previous sweep has completed h + H - 1 half-steps (one less than the rule
+    // asks), the rows of a right task up to p-2 and the columns of a left task up
+    // to p+b-2 are final: an exhaustive check of the schedule shows every earlier
+    // half-step that touches them is complete by then, for every stage shape.
+    // They are loaded and the reflector is generated first; the rest of the window
+    // is loaded, and everything is stored, only after the full wait.
+    const bool split = G == 1 && ga.prev != nullptr;
     double beta_row = 0.0;
     for (int P = 0; P < P_end; ++P) {
         // ---- dependency on the previous group (thread 0 polls, then acquires) ----
+        int need_b = 0;  // thread 0: the full condition of this phase
         if (tid == 0 && *s_ok && ga.prev) {
             int need = 0;
             for (int l = 0; l < nl; ++l) {
@@ -586,6 +612,8 @@ __device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
                 if (h + H > pred_len) need = kDone;        // predecessor must be DONE
                 else if (l == 0) need = max(need, h + H);  // lanes > 0 are covered by lock-step
             }
+            need_b = need;
+            if (split && need > 0) need = P + H - 1 > len_prev ? kDone : P + H - 1;
             if (need > known) {
                 const int v = poll_ge(ga.prev, need, ga.abort_flag, ga.err_word, ga.spin_limit);
                 if (v < 0) *s_ok = 0;
@@ -594,6 +622,18 @@ __device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
         }
         __syncthreads();
         if (!*s_ok) return false;
+        bool waited = false;
+        auto wait_b = [&]() -> bool {  // every thread of the workgroup
+            waited = true;
+            if (!split) return true;
+            if (tid == 0 && *s_ok && need_b > known) {
+                const int v = poll_ge(ga.prev, need_b, ga.abort_flag, ga.err_word, ga.spin_limit);
+                if (v < 0) *s_ok = 0;
+                else known = v;
+            }
+            __syncthreads();
+            return *s_ok != 0;
+        };
 
         // ---- this phase's half-step of every lane ----
         const int h = P - H * g;
@@ -602,15 +642,22 @@ __device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
         if (active) {
             sg = step_geom(n, b, tw, c, r, h >> 1);
             if ((h & 1) == 0) {
-                beta_row = right_task<T, TWM, NTL>(A, S, S32, sg, corner, scr, ltid);
+                beta_row = right_task<T, TWM, NTL>(A, S, S32, sg, corner, scr, ltid, split, wait_b);
             } else {
                 // row k of this step's right task (read by every wave of the lane in
-                // the previous phase) becomes (beta, 0, ..., 0)
-                if (defer_rowk && ltid <= sg.m)
-                    st_agent(to_global(A) + (sg.k + (int64_t)(sg.p + ltid) * S), static_cast<T>(ltid == 0 ? beta_row : 0.0));
-                left_task<T, TWM, NTL>(A, S, S32, sg, n, b, corner, stage, scr, ltid);
+                // the previous phase) becomes (beta, 0, ..., 0), after the full wait
+                auto wait_b_rowk = [&]() -> bool {
+                    if (!wait_b()) return false;
+                    if (defer_rowk && ltid <= sg.m)
+                        st_agent(to_global(A) + (sg.k + (int64_t)(sg.p + ltid) * S),
+                                 static_cast<T>(ltid == 0 ? beta_row : 0.0));
+                    return true;
+                };
+                left_task<T, TWM, NTL>(A, S, S32, sg, n, b, corner, stage, scr, ltid, split, wait_b_rowk);
             }
         }
+        if (!waited) wait_b();  // keeps the barrier count equal when no task ran
+        if (!*s_ok) return false;
         if (!defer_rowk) {
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();  // every wave of every lane has read its row k
