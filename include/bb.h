@@ -76,7 +76,7 @@ enum {
  *                      larger value only delays sweeps (results are unchanged).
  *   xcd_run            consecutive sweep groups placed on one XCD (accelerator
  *                      die with its own L2) before moving to the next (1..4096;
- *                      0 = automatic, 8), so that consecutive sweeps, whose
+ *                      0 = automatic, 2), so that consecutive sweeps, whose
  *                      windows overlap, share an L2.  Results do not depend on
  *                      it.  bb_reduce only; the batched form claims tasks in one
  *                      global order.

@@ -120,7 +120,7 @@ Launch resolve(int64_t n, int64_t b, int dtype, size_t lds_limit, bb_params_t p,
     L.lds_limit = lds_limit;
     L.groups_per_cu = p.groups_per_cu ? p.groups_per_cu : 2;
     L.lag = p.lag;
-    L.xcd_run = p.xcd_run ? p.xcd_run : 8;
+    L.xcd_run = p.xcd_run ? p.xcd_run : 2;
     // fit the workgroup's LDS (corners + staging blocks) and thread limits
     const int twm = bbp::kernel_twm(L.tw);
     while (L.lanes > 1 && bbk::stage_lds_bytes(dtype, twm, L.ntl, L.lanes) > lds_limit) --L.lanes;
@@ -662,7 +662,7 @@ extern "C" int bb_autotune(int64_t n, int64_t b, bb_dtype_t dtype, void* stream,
     // candidates: the built-in defaults and the shapes that win in some regime;
     // fields fixed by bb_set_params hold for every candidate
     std::vector<bb_params_t> cands = {{0, 0, 0, 0, 0, 0},   {0, 256, 1, 1, 0, 0}, {0, 0, 0, 1, 0, 0},
-                                      {16, 0, 0, 0, 0, 0},  {0, 0, 2, 0, 0, 0},   {0, 0, 0, 0, 0, 16},
+                                      {16, 0, 0, 0, 0, 0},  {0, 0, 2, 0, 0, 0},   {0, 0, 0, 0, 0, 8},
                                       {0, 128, 1, 2, 0, 0}, {8, 0, 0, 0, 0, 0}};
     for (bb_params_t& c : cands) {
         if (user.tw) c.tw = user.tw;

@@ -597,7 +597,9 @@ __device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
     // half-step that touches them is complete by then, for every stage shape.
     // They are loaded and the reflector is generated first; the rest of the window
     // is loaded, and everything is stored, only after the full wait.
-    const bool split = G == 1 && ga.prev != nullptr;
+    // (Measured: with c = 1, where the lag is 4 half-steps, the extra wait and
+    // barrier cost more than the early loads save, so that stage keeps one wait.)
+    const bool split = G == 1 && ga.prev != nullptr && c >= 2;
     double beta_row = 0.0;
     for (int P = 0; P < P_end; ++P) {
         // ---- dependency on the previous group (thread 0 polls, then acquires) ----
