@@ -150,11 +150,11 @@ __global__ void bb_fill_i32(int* __restrict__ p, int64_t count, int value) {
 // ---------------------------------------------------------------------------
 // Addressing.  A lane's window base is the same for every thread of a wave (a
 // wave never spans two lanes), so it is moved to scalar registers and every
-// access becomes scalar base + 32-bit unsigned byte offset (one VGPR per address).
+// window access becomes scalar base + 32-bit lane offset (see buf_ld / buf_st).
 // ---------------------------------------------------------------------------
-// Band pointers are kept in the global address space: generic (flat) accesses
-// would also count against the LDS wait counter, so every LDS wait would wait for
-// outstanding band loads as well.
+// Other band pointers are kept in the global address space: generic (flat)
+// accesses would also count against the LDS wait counter, so every LDS wait
+// would wait for outstanding band loads as well.
 template <typename T>
 using gptr = __attribute__((address_space(1))) T*;
 
@@ -188,15 +188,6 @@ __device__ __forceinline__ void st_agent(gptr<T> p, T v) {
         __hip_atomic_store(reinterpret_cast<gptr<unsigned short>>(p), __builtin_bit_cast(unsigned short, v),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-}
-
-// base + off elements with a 32-bit byte offset, so that a wave-uniform base in
-// scalar registers and one 32-bit offset per lane address the access (the host
-// keeps every in-window byte offset below 2^32).
-template <typename T>
-__device__ __forceinline__ gptr<T> at(gptr<T> base, int off) {
-    return reinterpret_cast<gptr<T>>(reinterpret_cast<gptr<char>>(base) +
-                                     static_cast<uint32_t>(off) * static_cast<uint32_t>(sizeof(T)));
 }
 
 // Window accesses of the two tasks go through raw buffer instructions: the
@@ -349,10 +340,12 @@ __device__ __forceinline__ int sweep_halfsteps(int n, int b, int c, int r) { ret
 // loaded and the reflector is generated before wait_b() (a workgroup barrier,
 // called by every thread) establishes the full condition for the other rows and
 // for every store.  wait_b() returns false if the pipeline was aborted.
+// With `rowk_now` (a one-wave lane that writes row k in its own phase) the wave
+// rewrites row k itself once its reflector has consumed the row.
 template <typename T, int TWM, int NTL, typename WaitB>
 __device__ __forceinline__ double right_task(T* __restrict__ A, int64_t S, int S32, StepGeom g,
                                              typename Compute<T>::type* corner, double* scr, int ltid,
-                                             bool split, WaitB&& wait_b) {
+                                             bool split, bool rowk_now, WaitB&& wait_b) {
     using C = typename Compute<T>::type;
     constexpr int LDC = TWM + 1;
     const int k = uni(g.k), p = uni(g.p), m = uni(g.m);  // a wave never spans two sweeps
@@ -368,6 +361,7 @@ __device__ __forceinline__ double right_task(T* __restrict__ A, int64_t S, int S
     double taud, betad;
     house_lds<TWM>(xl, m, scr, vs, taud, betad);
     if (!wait_b()) return betad;
+    if (rowk_now && ltid <= m) buf_st<T>(base, ltid * S32, 0, static_cast<T>(ltid == 0 ? betad : 0.0));
     if (!early) load_row<T, C, TWM>(av, base, S32, 1 + min(ri, rows - 1), m);
     const C tau = static_cast<C>(taud);
     while (ri < rows) {
@@ -600,6 +594,9 @@ __device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
     // (Measured: with c = 1, where the lag is 4 half-steps, the extra wait and
     // barrier cost more than the early loads save, so that stage keeps one wait.)
     const bool split = G == 1 && ga.prev != nullptr && c >= 2;
+    // A lane of one wave that writes row k in the same phase needs no barrier for
+    // it: no other wave reads the row, and the wave has consumed it by then.
+    const bool rowk_now = !defer_rowk && NTL == kWave;
     double beta_row = 0.0;
     for (int P = 0; P < P_end; ++P) {
         // ---- dependency on the previous group (thread 0 polls, then acquires) ----
@@ -644,7 +641,7 @@ __device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
         if (active) {
             sg = step_geom(n, b, tw, c, r, h >> 1);
             if ((h & 1) == 0) {
-                beta_row = right_task<T, TWM, NTL>(A, S, S32, sg, corner, scr, ltid, split, wait_b);
+                beta_row = right_task<T, TWM, NTL>(A, S, S32, sg, corner, scr, ltid, split, rowk_now, wait_b);
             } else {
                 // row k of this step's right task (read by every wave of the lane in
                 // the previous phase) becomes (beta, 0, ..., 0), after the full wait
@@ -660,7 +657,7 @@ __device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
         }
         if (!waited) wait_b();  // keeps the barrier count equal when no task ran
         if (!*s_ok) return false;
-        if (!defer_rowk) {
+        if (!defer_rowk && !rowk_now) {
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();  // every wave of every lane has read its row k
             if (active && (h & 1) == 0 && ltid <= sg.m)
