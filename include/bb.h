@@ -67,7 +67,8 @@ enum {
  *                      A stage whose kernel variant accepts fewer threads per
  *                      workgroup (256 for tw 17..32, 512 for 9..16) runs fewer
  *                      sweeps per group; results do not depend on it.
- *   groups_per_cu      persistent workgroups launched per compute unit (1..16);
+ *   groups_per_cu      persistent workgroups launched per compute unit (1..16;
+ *                      automatic: 2 for bb_reduce, 4 for bb_reduce_batched);
  *                      with sweeps_per_group it caps the sweeps in flight, the
  *                      paper's "Max blocks".
  *   lag                half-step dependency lag between consecutive sweeps; each

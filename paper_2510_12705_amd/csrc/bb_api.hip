@@ -100,7 +100,11 @@ bb_params_t current_params() {
 
 // Effective launch shape: a nonzero field of `p` wins, then a nonzero field of an
 // autotuned entry for this shape (if use_cache), then the built-in default.
-Launch resolve(int64_t n, int64_t b, int dtype, size_t lds_limit, bb_params_t p, bool use_cache = true) {
+// Workgroups per CU default to 2 for one band (more only lengthen each sweep's
+// half-steps) and to 4 for a batch, whose many independent sweeps fill every
+// workgroup the CU can hold (measured: 512 ragged FP32 bands 647 ms -> 392 ms).
+Launch resolve(int64_t n, int64_t b, int dtype, size_t lds_limit, bb_params_t p, bool use_cache = true,
+               int default_groups_per_cu = 2) {
     bbp::Tuned t;
     if (use_cache && bbp::autotune_lookup(n, b, dtype, &t)) {
         if (!p.tw) p.tw = t.p.tw;
@@ -118,7 +122,7 @@ Launch resolve(int64_t n, int64_t b, int dtype, size_t lds_limit, bb_params_t p,
     L.ntl_fixed = p.threads_per_window != 0;
     L.lanes_fixed = p.sweeps_per_group != 0;
     L.lds_limit = lds_limit;
-    L.groups_per_cu = p.groups_per_cu ? p.groups_per_cu : 2;
+    L.groups_per_cu = p.groups_per_cu ? p.groups_per_cu : default_groups_per_cu;
     L.lag = p.lag;
     L.xcd_run = p.xcd_run ? p.xcd_run : 2;
     // fit the workgroup's LDS (corners + staging blocks) and thread limits
@@ -512,7 +516,7 @@ int bb_reduce_batched(int64_t count, const int64_t* n, const int64_t* b, bb_dtyp
         max_n = std::max(max_n, n[i]);
         max_b = std::max(max_b, std::min(b[i], std::max<int64_t>(n[i] - 1, 0)));
     }
-    Launch L = resolve(max_n, max_b, dtype, ds->lds_per_block, current_params());
+    Launch L = resolve(max_n, max_b, dtype, ds->lds_per_block, current_params(), true, 4);
     if (L.tw < 1 || L.tw > bbp::kMaxTW) return BB_ERR_UNSUPPORTED;
     BatchPlan* bp = nullptr;
     rc = batch_plan(count, n, b, dtype, L, st, &bp);
