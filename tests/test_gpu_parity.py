@@ -97,10 +97,12 @@ def test_thread_and_lane_counts_are_bitwise_identical(bb, ntl, lanes):
     assert np.array_equal(d, ref[0]) and np.array_equal(e, ref[1])
 
 
-@pytest.mark.parametrize("ntl,lanes", [(64, 4), (128, 2), (256, 1), (256, 4)])
+@pytest.mark.parametrize("ntl,lanes", [(64, 4), (128, 2), (256, 1), (256, 4), (64, 1), (128, 1)])
 def test_tw32_group_shapes_are_bitwise_identical(bb, ntl, lanes):
     """The widest kernel variant (tw 17..32) takes at most 256 threads per workgroup;
-    larger requested groups are reduced by the host, never changing a bit."""
+    larger requested groups are reduced by the host, never changing a bit.  With one
+    sweep per workgroup and 64 or 128 threads the windows (up to 112 rows / columns)
+    exceed the threads, so the two-part wait meets multi-row and multi-block tasks."""
     n, b, tw = 900, 80, 32
     band = inputs.band_normal(n, b, seed=6)
     ref = gpu_reduce(bb, band, n, b, tw=tw, threads_per_window=256, sweeps_per_group=1)
