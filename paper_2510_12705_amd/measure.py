@@ -1,0 +1,77 @@
+"""Timings of the bandwidth sweep and the ragged batch on the GPU.
+
+    python -m paper_2510_12705_amd.measure c4   # n = 16384, b = 16 .. 256, FP64 / FP32 / FP16 storage
+    python -m paper_2510_12705_amd.measure c5   # 512 ragged FP32 bands: one batched call vs a loop
+
+Each case is timed as the best of two runs after one warm-up (host wall clock
+around the call and a device synchronisation), in the default launch
+configuration.  The roofline percentage divides the algorithmic bytes of the
+reference tilewidth schedule (one 128-byte line of the storage type) by the
+time and by MI355X's 8 TB/s.  Inputs come from ``inputs`` (synthetic, seeded).
+"""
+from __future__ import annotations
+
+import sys
+import time
+
+import numpy as np
+
+PEAK_BYTES_PER_S = 8.0e12
+TW_REF = {8: 16, 4: 32, 2: 64}
+
+
+def _best_ms(torch, fn, reps=2):
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        t = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t)
+    return best * 1e3
+
+
+def bandwidth_sweep(n=16384, bandwidths=(16, 32, 64, 128, 256)):
+    import torch
+
+    from . import bb, inputs
+    bb.reset_params()
+    for b in bandwidths:
+        band = torch.from_numpy(inputs.band_uniform(n, b, inputs.seed_for_bandwidth_sweep(b))).cuda()
+        out = []
+        for dt, elem in ((torch.float64, 8), (torch.float32, 4), (torch.float16, 2)):
+            t = band.to(dt)
+            ms = _best_ms(torch, lambda: bb.bb_reduce(t, n, b))
+            alg = bb.model_bytes(n, b, elem, TW_REF[elem])
+            out.append("%s %.1f ms (%.1f%% roofline)" % (str(dt).split(".")[-1], ms,
+                                                           100 * alg / (ms / 1e3) / PEAK_BYTES_PER_S))
+        print("n=%d b=%d: %s" % (n, b, " | ".join(out)), flush=True)
+
+
+def ragged_batch(count=512, seed=5):
+    import torch
+
+    from . import bb, inputs
+    bb.reset_params()
+    mats = inputs.ragged_batch(count=count, seed=seed)
+    bands = [torch.from_numpy(np.ascontiguousarray(bd)).cuda().to(torch.float32) for (_, _, bd) in mats]
+    ns = [m[0] for m in mats]
+    bs = [m[1] for m in mats]
+    ds = [torch.empty(max(x, 1), dtype=torch.float64, device="cuda") for x in ns]
+    es = [torch.empty(max(x, 1), dtype=torch.float64, device="cuda") for x in ns]
+    t_batch = _best_ms(torch, lambda: bb.bb_reduce_batched(bands, ns, bs, ds=ds, es=es))
+
+    def loop():
+        for t, x, y, d, e in zip(bands, ns, bs, ds, es):
+            bb.bb_reduce(t, x, y, d, e)
+
+    t_loop = _best_ms(torch, loop)
+    alg = sum(bb.model_bytes(x, y, 4, TW_REF[4]) for x, y in zip(ns, bs))
+    print("%d ragged FP32 bands: batched %.1f ms, loop of single calls %.1f ms (%.2fx); %.1f%% roofline" % (
+        count, t_batch, t_loop, t_loop / t_batch, 100 * alg / (t_batch / 1e3) / PEAK_BYTES_PER_S), flush=True)
+
+
+if __name__ == "__main__":
+    what = sys.argv[1] if len(sys.argv) > 1 else "c4"
+    {"c4": bandwidth_sweep, "c5": ragged_batch}[what]()

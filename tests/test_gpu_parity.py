@@ -328,6 +328,58 @@ def test_c3_fp64_properties_at_full_size(bb):
     assert abs(abs(e[0]) - np.linalg.norm(row0)) <= 8 * EPS64 * np.linalg.norm(row0)
 
 
+def _full_size_properties(band, n, b, d, e, eps, k):
+    """Properties that hold at any size: finite, Frobenius norm, sum sigma^4 =
+    ||A^T A||_F^2, d0 = a00 exactly, |e0| = ||A[0, 1:]|| (k: error multiplier)."""
+    assert np.isfinite(d).all() and np.isfinite(e).all()
+    A2 = np.sum(band * band)
+    assert abs(np.sum(d * d) + np.sum(e * e) - A2) <= k * n * eps * A2
+    B4 = np.sum((d * d + np.concatenate([[0.0], e * e])) ** 2) + 2.0 * np.sum((d[:-1] * e) ** 2)
+    A4 = _ata_frob2(band, n, b)
+    assert abs(B4 - A4) <= 2 * k * n * eps * A4
+    assert d[0] == band[0, b]
+    row0 = np.array([band[j, b - j] for j in range(1, b + 1)])
+    assert abs(abs(e[0]) - np.linalg.norm(row0)) <= 8 * eps * np.linalg.norm(row0) + k * eps * np.sqrt(A2)
+
+
+@pytest.mark.parametrize("b", [16, 256])
+def test_c4_fp64_properties_at_full_size(bb, b):
+    """The bandwidth sweep at its full size (n = 16384, U[-1, 1]) in the default launch
+    configuration: any-size properties and bitwise determinism."""
+    n = 16384
+    _say("case n=16384 b=%d fp64 properties" % b)
+    band = inputs.band_uniform(n, b, inputs.seed_for_bandwidth_sweep(b))
+    d, e = gpu_reduce(bb, band, n, b)
+    d2, e2 = gpu_reduce(bb, band, n, b)
+    assert np.array_equal(d, d2) and np.array_equal(e, e2)
+    _full_size_properties(band, n, b, d, e, EPS64, 20)
+
+
+def test_c5_ragged_batch_at_full_size(bb):
+    """All 512 ragged FP32 bands of the batch workload in one call with the default
+    (batched) launch configuration: a sample of 16 matrices is bitwise what one
+    bb_reduce per matrix gives, and every matrix keeps its Frobenius norm."""
+    _say("case 512 ragged fp32 batch")
+    mats = inputs.ragged_batch(count=512, seed=5)
+    bb.reset_params()
+    bands = [torch.from_numpy(np.ascontiguousarray(bd)).cuda().to(torch.float32) for (_, _, bd) in mats]
+    ns = [m[0] for m in mats]
+    bs = [m[1] for m in mats]
+    ds, es = bb.bb_reduce_batched(bands, ns, bs)
+    assert bb.stream_status() == 0
+    for i in range(0, 512, 32):
+        d1, e1 = bb.bb_reduce(bands[i], ns[i], bs[i])
+        assert np.array_equal(ds[i].cpu().numpy(), d1.cpu().numpy()), i
+        assert np.array_equal(es[i].cpu().numpy(), e1.cpu().numpy()), i
+    for t, n, dd, ee in zip(bands, ns, ds, es):
+        a = t.double().cpu().numpy()
+        A2 = np.sum(a * a)
+        d = dd.cpu().numpy()
+        e = ee.cpu().numpy()
+        assert np.isfinite(d).all() and np.isfinite(e).all()
+        assert abs(np.sum(d * d) + np.sum(e * e) - A2) <= 50 * n * EPS32 * A2
+
+
 # ------------------------------------------------------------------ ragged batch
 def _batch_case(count, seed, n_lo, n_hi, bands):
     return inputs.ragged_batch(count=count, seed=seed, n_lo=n_lo, n_hi=n_hi, bands=bands)
