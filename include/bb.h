@@ -51,7 +51,10 @@ enum {
     BB_ERR_HIP = 1,          /* a HIP runtime call failed */
     BB_ERR_TIMEOUT = 2,      /* device watchdog: a dependency wait never completed */
     BB_ERR_NOMEM = 3,        /* device or host allocation failed */
-    BB_ERR_UNSUPPORTED = 4,  /* parameters outside the compiled kernel variants */
+    BB_ERR_UNSUPPORTED = 4,  /* parameters outside the compiled kernel variants, or a band
+                                column height whose in-window byte offsets would exceed
+                                32 bits (working-band columns above about 5.4 million FP64
+                                entries; b is far smaller at any size that fits) */
     BB_ERR_NODEVICE = 5      /* no usable gfx950 device */
 };
 
