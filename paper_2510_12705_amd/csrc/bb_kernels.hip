@@ -304,11 +304,13 @@ __device__ __forceinline__ void store_row(const C (&av)[TWM + 1], Rsrc base, int
 // half-step exists).  Lane g then always trails lane g-1 by H half-steps, which
 // is exactly the dependency rule, so hand-over inside the group needs only the
 // workgroup barrier that ends each phase.  Lane 0 depends on the last sweep of
-// the previous group through that sweep's progress word (agent-scope
-// acquire by thread 0 before the phase); the group publishes the progress of
-// its own last sweep after every phase (agent-scope release by thread 0).
-// Concurrently running half-steps (of this and of other groups) touch
-// disjoint data, so results are bitwise those of the sequential order.
+// the previous group through that sweep's progress word (thread 0 polls it and
+// then acquires at agent scope); after every phase, once each wave has waited
+// for its agent-scope band stores, thread 0 publishes the progress of the
+// group's last sweep.  By default a group is one sweep (G = 1), whose phases
+// wait in two parts (see run_group).  Concurrently running half-steps (of this
+// and of other groups) touch disjoint data, so results are bitwise those of the
+// sequential order.
 // ---------------------------------------------------------------------------
 struct StepGeom {
     int k, p, m;
