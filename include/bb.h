@@ -125,6 +125,21 @@ int bb_reduce_batched(int64_t count, const int64_t *n, const int64_t *b, bb_dtyp
                       const void *const *band, const int64_t *ldband,
                       double *const *d, double *const *e, void *stream);
 
+/*
+ * Singular values of the upper bidiagonal B = bidiag(d, e) that bb_reduce
+ * returns (the paper computes them on the CPU, Sec. V-A; this is the on-device
+ * alternative).  sigma(B) are the non-negative eigenvalues of the 2n x 2n
+ * Golub-Kahan tridiagonal (zero diagonal, off-diagonal d0, e0, d1, ..., d_{n-1});
+ * one thread finds each by bisection on the Sturm count of that matrix, to an
+ * absolute accuracy of about 4 eps sigma_i + 2^-60 ||B||.
+ *   n        order (0 <= n <= 2^29).
+ *   d, e     device pointers to n and max(n - 1, 0) doubles (e may be NULL if n <= 1).
+ *   sigma    device pointer to n doubles: sigma_0 >= sigma_1 >= ... >= 0 (output).
+ *   stream   hipStream_t.  Asynchronous; allocates nothing.
+ * Argument numbers for -i: n=1, d=2, e=3, sigma=4.  NaN input gives NaN output.
+ */
+int bb_bidiag_sigma(int64_t n, const double *d, const double *e, double *sigma, void *stream);
+
 /* Set (p != NULL) or reset to automatic (p == NULL) the process-wide tuning
  * parameters; invalid values are rejected with -1 and leave the state unchanged. */
 int bb_set_params(const bb_params_t *p);

@@ -67,6 +67,8 @@ def _load():
     lib.bb_plan.restype = ctypes.c_int
     lib.bb_min_lag.argtypes = [i64]
     lib.bb_min_lag.restype = ctypes.c_int
+    lib.bb_bidiag_sigma.argtypes = [i64, vp, vp, vp, vp]
+    lib.bb_bidiag_sigma.restype = ctypes.c_int
     lib.bb_stream_status.argtypes = [vp]
     lib.bb_stream_status.restype = ctypes.c_int
     lib.bb_timing_enable.argtypes = [ctypes.c_int]
@@ -84,7 +86,7 @@ lib = _load()
 
 EXPORTS = ("bb_reduce", "bb_reduce_batched", "bb_set_params", "bb_get_params", "bb_autotune", "bb_resolved_params",
            "bb_workspace_bytes", "bb_model_bytes", "bb_plan", "bb_min_lag", "bb_stream_status",
-           "bb_release", "bb_error_string", "bb_timing_enable", "bb_timing_read")
+           "bb_release", "bb_error_string", "bb_timing_enable", "bb_timing_read", "bb_bidiag_sigma")
 
 
 def _check(rc: int, where: str):
@@ -124,6 +126,20 @@ def bb_reduce(band, n: int, b: int, d=None, e=None, stream=None, ldband: int | N
                        ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(e.data_ptr()), _stream_handle(stream))
     _check(rc, "bb_reduce")
     return d[:n], e[:max(n - 1, 0)]
+
+
+def bidiag_sigma(d, e, sigma=None, stream=None):
+    """Singular values (descending, float64 device tensor) of bidiag(d, e) given as
+    float64 device tensors, computed on the device.  Asynchronous on ``stream``."""
+    import torch
+    n = d.shape[0]
+    if sigma is None:
+        sigma = torch.empty(max(n, 1), dtype=torch.float64, device=d.device)
+    ep = e.data_ptr() if (e is not None and e.numel() > 0) else None
+    rc = lib.bb_bidiag_sigma(n, ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(ep),
+                             ctypes.c_void_p(sigma.data_ptr()), _stream_handle(stream))
+    _check(rc, "bb_bidiag_sigma")
+    return sigma[:n]
 
 
 def bb_reduce_batched(bands, ns, bs, ds=None, es=None, stream=None):

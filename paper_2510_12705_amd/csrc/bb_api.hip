@@ -579,6 +579,18 @@ int bb_plan(int64_t b, int tw, int max_stages, int* bs, int* tws, int* cs, int* 
 
 int bb_min_lag(int64_t c) { return c < 1 ? -1 : bbp::min_lag((int)std::min<int64_t>(c, 1 << 20)); }
 
+int bb_bidiag_sigma(int64_t n, const double* d, const double* e, double* sigma, void* stream) {
+    if (n < 0 || n > (int64_t(1) << 29)) return -1;
+    if (n > 0 && !d) return -2;
+    if (n > 1 && !e) return -3;
+    if (n > 0 && !sigma) return -4;
+    if (n == 0) return BB_OK;
+    DeviceState* ds = nullptr;
+    int rc = device_state(&ds);
+    if (rc) return rc;
+    return check_hip(bbk::launch_bidiag_sigma(d, e, n, sigma, (hipStream_t)stream));
+}
+
 int bb_stream_status(void* stream) {
     DeviceState* ds = nullptr;
     int rc = device_state(&ds);

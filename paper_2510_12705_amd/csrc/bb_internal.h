@@ -72,6 +72,8 @@ hipError_t launch_fill_synth(int dtype, void* p, int64_t count, uint64_t seed, h
 hipError_t launch_f16_rescale(void* W, int64_t count, unsigned* amax, int* exps, int s, hipStream_t st);
 hipError_t launch_extract_f16(const void* W, int64_t n, int64_t ldw, int64_t uo, const int* exps, int nexp,
                               double* d, double* e, hipStream_t st);
+// sigma of bidiag(d, e), descending, by bisection on the Golub-Kahan tridiagonal
+hipError_t launch_bidiag_sigma(const double* d, const double* e, int64_t n, double* sigma, hipStream_t st);
 // largest workgroup (ntl * lanes) the stage kernel variant for tilewidth bound twm accepts
 int stage_max_threads(int twm);
 // dynamic LDS bytes of one stage workgroup (lanes corners + per-wave staging blocks)

@@ -2,6 +2,7 @@
 
     python -m paper_2510_12705_amd.measure c4   # n = 16384, b = 16 .. 256, FP64 / FP32 / FP16 storage
     python -m paper_2510_12705_amd.measure c5   # 512 ragged FP32 bands: one batched call vs a loop
+    python -m paper_2510_12705_amd.measure sigma  # sigma of the n = 32768 bidiagonal on the device
 
 Each case is timed as the best of two runs after one warm-up (host wall clock
 around the call and a device synchronisation), in the default launch
@@ -72,6 +73,38 @@ def ragged_batch(count=512, seed=5):
         count, t_batch, t_loop, t_loop / t_batch, 100 * alg / (t_batch / 1e3) / PEAK_BYTES_PER_S), flush=True)
 
 
+def bidiag_sigma(n=32768, b=128):
+    """sigma of the bidiagonal that the n = 32768, b = 128 reduction returns: the device
+    bisection (bb_bidiag_sigma) against LAPACK dsterf on the host (one core), the
+    routine the CPU reference uses on the same Golub-Kahan tridiagonal."""
+    import torch
+
+    from . import bb, inputs
+    bb.reset_params()
+    band = torch.from_numpy(inputs.workload("n%d_b%d" % (n, b))).cuda()
+    d, e = bb.bb_reduce(band, n, b)
+    torch.cuda.synchronize()
+    ms = _best_ms(torch, lambda: bb.bidiag_sigma(d, e))
+    sig = bb.bidiag_sigma(d, e).cpu().numpy()
+    from scipy.linalg import lapack
+    off = np.zeros(2 * n - 1)
+    off[0::2] = d.cpu().numpy()
+    off[1::2] = e.cpu().numpy()[: n - 1]
+    t = time.perf_counter()
+    w, info = lapack.dsterf(np.zeros(2 * n), off)
+    host_ms = (time.perf_counter() - t) * 1e3
+    ref = np.sort(w)[::-1][:n].clip(min=0.0)
+    # Sturm-count work: 8 lanes per value, ~19 multisection steps (each divides the
+    # interval by 9 down to 2^-60 of the bound), 2n pivots of one division and two
+    # multiply-adds per count
+    evals = 8 * 19
+    flops = float(n) * evals * 2 * n * 4
+    print("n=%d: device multisection %.1f ms (%.0f GFLOP/s of Sturm counts), host dsterf %.1f ms (%.0fx); "
+          "max |sigma_dev - sigma_dsterf| / sigma_max = %.2e" % (
+              n, ms, flops / (ms / 1e3) / 1e9, host_ms, host_ms / ms, np.max(np.abs(sig - ref)) / ref[0]),
+          flush=True)
+
+
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "c4"
-    {"c4": bandwidth_sweep, "c5": ragged_batch}[what]()
+    {"c4": bandwidth_sweep, "c5": ragged_batch, "sigma": bidiag_sigma}[what]()

@@ -53,6 +53,11 @@ def test_argument_validation_without_device():
     assert L.bb_reduce_batched(1, I64(8), I64(4), 0, VP(0x1000), I64(2), VP(0x1000), VP(0x1000), None) == -6
     assert L.bb_reduce_batched(1, I64(8), I64(4), 9, VP(0x1000), I64(5), VP(0x1000), VP(0x1000), None) == -4
     assert L.bb_reduce_batched(0, None, None, 0, None, None, None, None, None) == 0
+    assert L.bb_bidiag_sigma(-1, dummy, dummy, dummy, None) == -1
+    assert L.bb_bidiag_sigma(4, None, dummy, dummy, None) == -2
+    assert L.bb_bidiag_sigma(4, dummy, None, dummy, None) == -3
+    assert L.bb_bidiag_sigma(4, dummy, dummy, None, None) == -4
+    assert L.bb_bidiag_sigma(0, None, None, None, None) == 0       # n = 0 is a no-op
     assert bb.bb_error_string(-3) == "invalid argument"
     assert "watchdog" in bb.bb_error_string(2)
 

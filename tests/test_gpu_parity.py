@@ -380,6 +380,73 @@ def test_c5_ragged_batch_at_full_size(bb):
         assert abs(np.sum(d * d) + np.sum(e * e) - A2) <= 50 * n * EPS32 * A2
 
 
+# ------------------------------------------------------------------ sigma of the bidiagonal on the device
+def _gpu_sigma(bb, d, e):
+    dt = torch.from_numpy(np.ascontiguousarray(d, dtype=np.float64)).cuda()
+    et = torch.from_numpy(np.ascontiguousarray(e, dtype=np.float64)).cuda()
+    s = bb.bidiag_sigma(dt, et)
+    torch.cuda.synchronize()
+    return s.cpu().numpy()
+
+
+def _check_sigma(bb, d, e):
+    n = len(d)
+    s_gpu = _gpu_sigma(bb, d, e)
+    s_ref = oracle.singular_values(d, e)
+    assert np.all(np.diff(s_gpu) <= 0) and np.all(s_gpu >= 0)
+    tol = 20 * n * EPS64 * max(s_ref[0], 1e-300)
+    assert np.max(np.abs(s_gpu - s_ref)) <= tol, (np.max(np.abs(s_gpu - s_ref)), tol)
+    return s_gpu, s_ref
+
+
+@pytest.mark.parametrize("n,seed", [(1, 1), (2, 2), (3, 3), (100, 4), (1000, 5), (4097, 6)])
+def test_bidiag_sigma_matches_oracle(bb, n, seed):
+    """sigma(bidiag(d, e)) by bisection on the device against the oracle's LAPACK
+    dsterf on the same Golub-Kahan tridiagonal."""
+    _say("case bidiag sigma n=%d" % n)
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal(n)
+    e = rng.standard_normal(max(n - 1, 0))
+    _check_sigma(bb, d, e)
+
+
+def test_bidiag_sigma_special_cases(bb):
+    """Diagonal input (sigma = sorted |d|, exactly up to the bisection width), zeros,
+    a graded spectrum and a 2 x 2 closed form."""
+    _say("case bidiag sigma special cases")
+    d = np.array([3.0, -1.0, 0.0, 2.0, -7.5])
+    s = _gpu_sigma(bb, d, np.zeros(4))
+    assert np.allclose(s, np.sort(np.abs(d))[::-1], rtol=8 * EPS64, atol=1e-18 * 7.5)
+    assert np.all(_gpu_sigma(bb, np.zeros(6), np.zeros(5)) == 0.0)
+    n = 300
+    d = 10.0 ** (-6.0 * np.arange(n) / n)
+    e = 0.5 * 10.0 ** (-6.0 * np.arange(1, n) / n)
+    _check_sigma(bb, d, e)
+    a, b, c = 3.0, 4.0, 2.0        # B = [[a, b], [0, c]]
+    fro2, det = a * a + b * b + c * c, abs(a * c)
+    smax = np.sqrt((fro2 + np.sqrt(fro2 * fro2 - 4 * det * det)) / 2)
+    s = _gpu_sigma(bb, np.array([a, c]), np.array([b]))
+    assert abs(s[0] - smax) <= 8 * EPS64 * smax and abs(s[1] - det / smax) <= 8 * EPS64 * smax
+
+
+def test_bidiag_sigma_after_reduction(bb):
+    """The full second + third stage on the device: reduce the n = 8192, b = 64 band,
+    then sigma of the result, against the oracle's sigma of the same (d, e) and, through
+    the bitwise reduction parity, of the oracle's own bidiagonal."""
+    n, b = 8192, 64
+    _say("case reduction + device sigma n=8192 b=64")
+    band = inputs.workload("n8192_b64")
+    t = torch.from_numpy(band).cuda()
+    d, e = bb.bb_reduce(t, n, b)
+    s = bb.bidiag_sigma(d, e)
+    torch.cuda.synchronize()
+    s = s.cpu().numpy()
+    s_ref = oracle.singular_values(d.cpu().numpy(), e.cpu().numpy())
+    assert np.max(np.abs(s - s_ref)) <= 20 * n * EPS64 * s_ref[0]
+    A2 = np.sum(band * band)
+    assert abs(np.sum(s * s) - A2) <= 40 * n * EPS64 * A2
+
+
 # ------------------------------------------------------------------ ragged batch
 def _batch_case(count, seed, n_lo, n_hi, bands):
     return inputs.ragged_batch(count=count, seed=seed, n_lo=n_lo, n_hi=n_hi, bands=bands)
