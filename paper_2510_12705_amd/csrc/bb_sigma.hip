@@ -15,7 +15,7 @@
 // multisection of [0, Gershgorin bound]: each lane evaluates the count at one of
 // kSect equally spaced interior points, and the group keeps the subinterval with
 // count(lo) <= t < count(hi), so every step divides the interval by kSect + 1
-// (about 19 steps instead of 62 bisections), until it is below 4 eps of its
+// (about 26 steps instead of 62 bisections), until it is below 4 eps of its
 // upper end or 2^-60 of the bound.  The count is a serial chain of divisions;
 // more lanes per value also give each SIMD more waves to hide its latency.
 // Every lane walks the same entries in the same order, so the loads of d and e
@@ -48,7 +48,7 @@ __device__ __forceinline__ int tgk_count_below(const double* __restrict__ d, con
     return cnt;
 }
 
-constexpr int kSect = 8;  // lanes per singular value (divides the wave size)
+constexpr int kSect = 4;  // lanes per singular value (divides the wave size; 4 measured fastest)
 
 __global__ void bb_tgk_bisect(const double* __restrict__ d, const double* __restrict__ e, int n,
                               double* __restrict__ sigma) {

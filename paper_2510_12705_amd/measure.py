@@ -94,10 +94,10 @@ def bidiag_sigma(n=32768, b=128):
     w, info = lapack.dsterf(np.zeros(2 * n), off)
     host_ms = (time.perf_counter() - t) * 1e3
     ref = np.sort(w)[::-1][:n].clip(min=0.0)
-    # Sturm-count work: 8 lanes per value, ~19 multisection steps (each divides the
-    # interval by 9 down to 2^-60 of the bound), 2n pivots of one division and two
+    # Sturm-count work: 4 lanes per value, ~26 multisection steps (each divides the
+    # interval by 5 down to 2^-60 of the bound), 2n pivots of one division and two
     # multiply-adds per count
-    evals = 8 * 19
+    evals = 4 * 26
     flops = float(n) * evals * 2 * n * 4
     print("n=%d: device multisection %.1f ms (%.0f GFLOP/s of Sturm counts), host dsterf %.1f ms (%.0fx); "
           "max |sigma_dev - sigma_dsterf| / sigma_max = %.2e" % (
