@@ -29,7 +29,8 @@
  *   - Errors: 0 on success; -i if argument i (1-based) is invalid, with no
  *     work enqueued; > 0 for a runtime failure (BB_ERR_*).  Nothing aborts.
  *     A device-side watchdog on every dependency wait turns a stalled pipeline
- *     into BB_ERR_TIMEOUT, reported by bb_stream_status().
+ *     into BB_ERR_TIMEOUT, reported by bb_stream_status() (one error word per
+ *     device).
  *   - Edge cases: n = 0 is a no-op; n = 1 gives d0 = a00; b = 0 gives d =
  *     diagonal, e = 0; b = 1 is copied through; b >= n is treated as n - 1.
  *     NaN / Inf in the input propagate to the output.
@@ -108,7 +109,9 @@ int bb_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void *band, int64_t 
 
 /*
  * Reduce `count` independent bands of uneven n_i, b_i in one persistent launch
- * that draws (matrix, stage, sweep) tasks from a device work queue.  All host
+ * that draws (matrix, stage, sweep) tasks from a device work queue.  The paper
+ * has no batched form: this entry point is this library's addition; each
+ * matrix undergoes exactly the reduction of bb_reduce (Sec. III, Algorithm 1).  All host
  * arrays have `count` entries; band[i], d[i], e[i] are device pointers as in
  * bb_reduce.  Argument numbers: count=1, n=2, b=3, dtype=4, band=5, ldband=6,
  * d=7, e=8.  A matrix with an invalid entry makes the whole call fail with
@@ -117,9 +120,10 @@ int bb_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void *band, int64_t 
  * builds a plan and allocates its device workspace (hipMalloc); later calls
  * with the same key reuse it and allocate nothing, so they may be captured
  * into a hipGraph (the captured copy of the pointer arrays reads them from a
- * pinned host buffer at replay time: replays use the pointers of the most
- * recent call with that key).  Calls sharing a plan must not overlap in time;
- * bb_release() frees all plans.
+ * pinned host buffer kept for captures at replay time: replays use the
+ * pointers of the most recent CAPTURED call with that key; direct calls stage
+ * theirs in a separate buffer).  Calls sharing a plan must not overlap in
+ * time; bb_release() frees all plans.
  */
 int bb_reduce_batched(int64_t count, const int64_t *n, const int64_t *b, bb_dtype_t dtype,
                       const void *const *band, const int64_t *ldband,
@@ -147,7 +151,11 @@ int bb_set_params(const bb_params_t *p);
 int bb_get_params(bb_params_t *p);
 
 /*
- * Autotune for one problem shape: a short list of parameter sets (the built-in
+ * Autotune for one problem shape.  The paper tunes its three knobs (threads per
+ * block, inner tilewidth, maximum blocks; Sec. III-C and the hyper-parameter
+ * study of Sec. V) by brute-force search and names automatic tuning as future
+ * work (Sec. VII); this is that search, ranked by a model and judged by time.
+ * A short list of parameter sets (the built-in
  * defaults and shapes that win in other regimes; fields fixed by bb_set_params
  * are kept in all of them) is ranked by a critical-path model, the best six are
  * timed on a synthetic band of this shape (n capped at 32768) on `stream`, and
@@ -164,7 +172,10 @@ int bb_autotune(int64_t n, int64_t b, bb_dtype_t dtype, void *stream, bb_params_
  * only; no device work.  -4 if out is NULL. */
 int bb_resolved_params(int64_t n, int64_t b, bb_dtype_t dtype, bb_params_t *out);
 
-/* Device bytes of working memory one bb_reduce call of this shape allocates. */
+/* Device bytes of working memory one bb_reduce call of this shape allocates: the
+ * working band of b + 2 TW + 1 rows per column (the band height given in the
+ * storage paragraph of Sec. IV) plus the dependency counters.  Not in the paper;
+ * a sizing query of this library.  0 for n <= 0 or b < 0. */
 size_t bb_workspace_bytes(int64_t n, int64_t b, bb_dtype_t dtype);
 
 /*
@@ -186,8 +197,11 @@ int bb_plan(int64_t b, int tw, int max_stages, int *bs, int *tws, int *cs, int *
 /* Smallest safe half-step lag for a stage that leaves bandwidth c (c >= 1). */
 int bb_min_lag(int64_t c);
 
-/* Synchronise `stream` and return (and clear) the device's error word:
- * BB_OK or BB_ERR_TIMEOUT, or BB_ERR_HIP if the synchronisation failed. */
+/* Synchronise `stream` and return (and clear) the error word of the current
+ * device: BB_OK or BB_ERR_TIMEOUT, or BB_ERR_HIP if the synchronisation failed.
+ * The error word is kept per DEVICE, not per stream: a watchdog timeout raised
+ * by a call on another stream of the same device is reported (and cleared) by
+ * whichever bb_stream_status call reads it first. */
 int bb_stream_status(void *stream);
 
 /*

@@ -13,6 +13,7 @@ Contents
   * ``reduce_dense_full`` -- an independent pure-Python coding on a dense matrix that
                              applies every reflector to all rows and columns (no index
                              ranges at all), for pinning the band code's ranges.
+  * ``nrm2``              -- the C oracle's norm on its own, for its pins.
   * ``singular_values``   -- sigma of a bidiagonal (d, e) as the non-negative
                              eigenvalues of its Golub-Kahan (TGK) tridiagonal, via
                              LAPACK dsterf; the paper uses LAPACK BDSDC for this step
@@ -57,6 +58,8 @@ def _load():
         lib.bbo_reduce_pipelined.argtypes = [i64, i64, i64, dp, i64, dp, dp,
                                              ctypes.POINTER(ctypes.c_int), ctypes.c_uint64]
         lib.bbo_reduce_pipelined.restype = ctypes.c_int
+        lib.bbo_nrm2.argtypes = [dp, i64]
+        lib.bbo_nrm2.restype = ctypes.c_double
         _lib = lib
     return _lib
 
@@ -89,6 +92,12 @@ def reduce(band: np.ndarray, n: int, b: int, tw: int, want_uv: bool = False, rev
     if want_uv:
         return d, e, U, V
     return d, e
+
+
+def nrm2(x) -> float:
+    """The C oracle's Euclidean norm (LAPACK >= 3.10 xNRM2) of a float64 vector."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    return float(_load().bbo_nrm2(_dp(x), x.shape[0]))
 
 
 def reduce_pipelined(band: np.ndarray, n: int, b: int, tw: int, lag, seed: int):

@@ -97,6 +97,9 @@ static double nrm2(const double *x, int64_t len) {
     return scl * sqrt(sumsq);
 }
 
+/* Exported for the pins of the norm itself (tests call it directly). */
+double bbo_nrm2(const double *x, int64_t len) { return nrm2(x, len); }
+
 /* sqrt(a^2 + b^2) without avoidable overflow (LAPACK xLAPY2). */
 static double hypot2(double a, double b) {
     double xa = fabs(a), ya = fabs(b);

@@ -21,13 +21,16 @@ namespace {
 
 constexpr int kMaxXcd = 16;  // per-XCD claim counters kept per stage
 
+// The device's error word (watchdog): written by kernels, read and cleared by
+// bb_stream_status.  A device global, so that setting up a device allocates nothing.
+__device__ int g_err_word;
+
 struct DeviceState {
     bool init = false;
     int cus = 0;
     size_t lds_per_block = 65536;  // largest dynamic LDS allocation of one workgroup
     int nxcd = 1;                  // XCDs (accelerator complex dies), each with its own L2
-    int* err_host = nullptr;  // host-mapped error word
-    int* err_dev = nullptr;
+    int* err_dev = nullptr;        // this device's copy of g_err_word
 };
 
 std::mutex g_mu;
@@ -63,11 +66,7 @@ int device_state(DeviceState** out) {
         int nx = 1;
         if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, dev) == hipSuccess && nx >= 1)
             s.nxcd = std::min(nx, (int)kMaxXcd);
-        if (hipHostMalloc((void**)&s.err_host, sizeof(int), hipHostMallocMapped | hipHostMallocCoherent) !=
-            hipSuccess)
-            return BB_ERR_NOMEM;
-        *s.err_host = 0;
-        if (hipHostGetDevicePointer((void**)&s.err_dev, s.err_host, 0) != hipSuccess) return BB_ERR_HIP;
+        if (hipGetSymbolAddress((void**)&s.err_dev, HIP_SYMBOL(g_err_word)) != hipSuccess) return BB_ERR_HIP;
         hipMemPool_t pool;
         if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
             uint64_t thr = UINT64_MAX;  // keep freed working memory cached in the pool
@@ -155,11 +154,10 @@ struct Workspace {
 
 Workspace workspace_layout(int64_t n, int64_t b, int dtype, int tw) {
     Workspace w;
-    bbp::Plan plan = bbp::make_plan(b, tw);
-    int tw0 = plan.stages.empty() ? 0 : plan.stages[0].tw;
+    const int tw0 = b > 1 ? bbp::stage_first(b, tw).tw : 0;
     w.uo = std::max<int64_t>(b + tw0, 1);
     w.ldw = align_up((size_t)(w.uo + tw0 + 1), 2);
-    w.nstages = (int)plan.stages.size();
+    w.nstages = bbp::stage_count(b, tw);
     w.max_sweeps = std::max<int64_t>(n, 1);
     w.band_bytes = align_up((size_t)(n * w.ldw) * elem_size(dtype), 256);
     w.off_claim = w.nstages * w.max_sweeps;
@@ -172,6 +170,17 @@ Workspace workspace_layout(int64_t n, int64_t b, int dtype, int tw) {
 }
 
 int check_hip(hipError_t e) { return e == hipSuccess ? BB_OK : BB_ERR_HIP; }
+
+// Read (and with `clear`, reset) the device's error word; the caller has synchronised.
+int read_err_word(DeviceState* ds, bool clear) {
+    int v = 0;
+    if (hipMemcpy(&v, ds->err_dev, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return BB_ERR_HIP;
+    if (v && clear) {
+        const int z = 0;
+        if (hipMemcpy(ds->err_dev, &z, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) return BB_ERR_HIP;
+    }
+    return v;
+}
 
 // The stage kernels address a window with 32-bit byte offsets from a wave-uniform
 // base; the largest spans kWave + TW + 2 band columns.  True when they fit.
@@ -187,9 +196,10 @@ bool window_offsets_fit(const Workspace& w, int dtype) {
 // different streams get different plans.
 // ---------------------------------------------------------------------------
 struct BatchPlan {
-    uint64_t key = 0;
+    uint64_t key = 0;  // hash of the fields below: a pre-filter only, matched exactly after it
     hipStream_t stream = nullptr;
-    int count = 0, dtype = 0, tw = 0, ntl = 0, lanes = 0, twm = 0;
+    int count = 0, dtype = 0, tw = 0, ntl = 0, lanes = 0, twm = 0, lag = 0;
+    std::vector<int64_t> ns, bs;  // the caller's n[] and b[]
     int64_t max_elems = 0, max_n = 0;
     int ntasks = 0, nprogress = 0, nexps = 0;
     std::vector<bbk::BatchMatrix> mats;
@@ -199,9 +209,19 @@ struct BatchPlan {
     size_t dev_bytes = 0;
     size_t off_counters = 0, off_mats = 0, off_stages = 0, off_tasks = 0, off_ptrs = 0;
     int64_t ncounters = 0;
-    void* pinned = nullptr;  // staging for the per-call pointer arrays
+    void* pinned = nullptr;          // staging for the pointer arrays of direct (uncaptured) calls
+    void* pinned_capture = nullptr;  // staging read by captured copies when a graph is replayed
     hipEvent_t staged = nullptr;
     bool staged_pending = false;
+
+    bool matches(int64_t cnt, const int64_t* n, const int64_t* b, int dt, const Launch& L, hipStream_t st) const {
+        if (stream != st || count != cnt || dtype != dt || tw != L.tw || ntl != L.ntl || lanes != L.lanes ||
+            lag != L.lag)
+            return false;
+        for (int64_t i = 0; i < cnt; ++i)
+            if (ns[(size_t)i] != n[i] || bs[(size_t)i] != b[i]) return false;
+        return true;
+    }
 };
 
 std::vector<BatchPlan*> g_batch_plans;
@@ -213,13 +233,14 @@ uint64_t mix(uint64_t h, uint64_t v) {
 
 int batch_plan(int64_t count, const int64_t* n, const int64_t* b, int dtype, const Launch& L, hipStream_t st,
                BatchPlan** out) {
-    uint64_t key = mix(mix(mix(mix(mix(0, (uint64_t)count), (uint64_t)dtype), (uint64_t)L.tw), (uint64_t)L.ntl),
-                       (uint64_t)L.lanes);
+    uint64_t key = mix(mix(mix(mix(mix(mix(0, (uint64_t)count), (uint64_t)dtype), (uint64_t)L.tw), (uint64_t)L.ntl),
+                           (uint64_t)L.lanes),
+                       (uint64_t)L.lag);
     for (int64_t i = 0; i < count; ++i) key = mix(mix(key, (uint64_t)n[i]), (uint64_t)b[i]);
     {
         std::lock_guard<std::mutex> lk(g_mu);
         for (BatchPlan* p : g_batch_plans)
-            if (p->key == key && p->stream == st) {
+            if (p->key == key && p->matches(count, n, b, dtype, L, st)) {
                 *out = p;
                 return BB_OK;
             }
@@ -237,6 +258,9 @@ int batch_plan(int64_t count, const int64_t* n, const int64_t* b, int dtype, con
     P->tw = L.tw;
     P->ntl = L.ntl;
     P->lanes = L.lanes;
+    P->lag = L.lag;
+    P->ns.assign(n, n + count);
+    P->bs.assign(b, b + count);
     P->twm = bbp::kernel_twm(L.tw);
     size_t band_off = 0;
     std::vector<size_t> band_offs((size_t)count);
@@ -301,7 +325,10 @@ int batch_plan(int64_t count, const int64_t* n, const int64_t* b, int dtype, con
     }
     for (int64_t i = 0; i < count; ++i) P->mats[(size_t)i].W = P->dev + band_offs[(size_t)i];
     if (hipHostMalloc(&P->pinned, 4 * sizeof(void*) * (size_t)count, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&P->pinned_capture, 4 * sizeof(void*) * (size_t)count, hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&P->staged, hipEventDisableTiming) != hipSuccess) {
+        if (P->pinned) (void)hipHostFree(P->pinned);
+        if (P->pinned_capture) (void)hipHostFree(P->pinned_capture);
         (void)hipFree(P->dev);
         delete P;
         return BB_ERR_NOMEM;
@@ -326,14 +353,17 @@ int batch_plan(int64_t count, const int64_t* n, const int64_t* b, int dtype, con
 int batch_run(BatchPlan* P, DeviceState* ds, const void* const* band, const int64_t* ldband, double* const* d,
               double* const* e, const Launch& L, hipStream_t st) {
     const size_t cnt = (size_t)P->count;
-    // The staging buffer may still feed the previous call's copy.  While the stream
-    // is being captured into a graph nothing is executed, and the captured copy
-    // reads the staging buffer when the graph is replayed.
+    // Direct calls stage the pointer arrays in `pinned`, which may still feed the
+    // previous direct call's copy (hence the event wait).  A call captured into a
+    // graph executes nothing now: its copy reads `pinned_capture` whenever the graph
+    // is replayed, so direct calls never overwrite what a queued replay reads, and
+    // a capture never overwrites what a queued direct copy reads.  Replays use the
+    // pointers of the most recent capture with this plan.
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) != hipSuccess) return BB_ERR_HIP;
     const bool capturing = cs != hipStreamCaptureStatusNone;
     if (!capturing && P->staged_pending && hipEventSynchronize(P->staged) != hipSuccess) return BB_ERR_HIP;
-    void** host = static_cast<void**>(P->pinned);
+    void** host = static_cast<void**>(capturing ? P->pinned_capture : P->pinned);
     for (size_t i = 0; i < cnt; ++i) {
         host[i] = const_cast<void*>(band[i]);
         host[cnt + i] = reinterpret_cast<void*>(ldband[i]);
@@ -382,6 +412,7 @@ void batch_plans_clear() {
         if (p->staged_pending) (void)hipEventSynchronize(p->staged);
         (void)hipEventDestroy(p->staged);
         (void)hipHostFree(p->pinned);
+        (void)hipHostFree(p->pinned_capture);
         (void)hipFree(p->dev);
         delete p;
     }
@@ -412,32 +443,45 @@ int bb_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, int64_t 
     return reduce_impl(n, b, dtype, band, ldband, d, e, (hipStream_t)stream, ds, current_params(), true);
 }
 
-// Body of bb_reduce for validated arguments, with explicit parameters.
-static int reduce_impl(int64_t n, int64_t b, int dtype, const void* band, int64_t ldband, double* d, double* e,
-                       hipStream_t st, DeviceState* ds, const bb_params_t& params, bool use_cache) {
-    int rc = BB_OK;
-    const int64_t b_in = b;
-    const int64_t bb = std::min<int64_t>(b, n - 1);
-    Launch L = resolve(n, bb, dtype, ds->lds_per_block, params, use_cache);
-    if (L.tw < 1 || L.tw > bbp::kMaxTW) return BB_ERR_UNSUPPORTED;
-    bbp::Plan plan = bbp::make_plan(bb, L.tw);
-    Workspace ws = workspace_layout(n, bb, dtype, L.tw);
-    if (!window_offsets_fit(ws, dtype)) return BB_ERR_UNSUPPORTED;
+// A validated bb_reduce call: launch shape and working-memory layout.
+struct Call {
+    int64_t n = 0, b_in = 0, bb = 0;  // order, caller's bandwidth, bandwidth clamped to n - 1
+    int dtype = 0;
+    Launch L{};
+    Workspace ws{};
+};
 
-    void* base = nullptr;
-    if (hipMallocAsync(&base, ws.total, st) != hipSuccess) return BB_ERR_NOMEM;
-    char* W = (char*)base;
-    int* counters = (int*)((char*)base + ws.band_bytes);
-    const int64_t ncounters = ws.ncounters;
+static int prepare_call(int64_t n, int64_t b, int dtype, DeviceState* ds, const bb_params_t& params, bool use_cache,
+                        Call* c) {
+    c->n = n;
+    c->b_in = b;
+    c->bb = std::min<int64_t>(b, n - 1);
+    c->dtype = dtype;
+    c->L = resolve(n, c->bb, dtype, ds->lds_per_block, params, use_cache);
+    if (c->L.tw < 1 || c->L.tw > bbp::kMaxTW) return BB_ERR_UNSUPPORTED;
+    c->ws = workspace_layout(n, c->bb, dtype, c->L.tw);
+    if (!window_offsets_fit(c->ws, dtype)) return BB_ERR_UNSUPPORTED;
+    return BB_OK;
+}
+
+// Enqueue the whole reduction on `st` with working memory at `base` (c.ws.total
+// bytes, 256-byte aligned): zero the counters, pack, one stage kernel per
+// bandwidth-reduction stage, extract.  Allocates nothing on the device; with
+// `timing_allowed` and timing enabled it creates one event pair per stage launch.
+static int enqueue_call(const Call& c, const void* band, int64_t ldband, double* d, double* e, hipStream_t st,
+                        DeviceState* ds, char* base, bool timing_allowed) {
+    const Launch& L = c.L;
+    const Workspace& ws = c.ws;
+    const int64_t n = c.n;
+    const int dtype = c.dtype;
+    char* W = base;
+    int* counters = (int*)(base + ws.band_bytes);
     unsigned* f16_amax = (unsigned*)(counters + ws.off_amax);  // one word per stage
     int* f16_exps = counters + ws.off_exps;                     // nstages + 1 exponents
-
-    float scale = 1.0f;
-    double inv_scale = 1.0;
-    rc = check_hip(bbk::launch_fill(counters, ncounters, 0, st));
-    if (!rc) rc = check_hip(bbk::launch_pack(dtype, band, ldband, n, b_in, bb, W, ws.ldw, ws.uo, scale, st));
-    for (int s = 0; s < ws.nstages && !rc; ++s) {
-        const bbp::Stage& sg = plan.stages[s];
+    int rc = check_hip(bbk::launch_fill(counters, ws.ncounters, 0, st));
+    if (!rc) rc = check_hip(bbk::launch_pack(dtype, band, ldband, n, c.b_in, c.bb, W, ws.ldw, ws.uo, 1.0f, st));
+    bbp::Stage sg = c.bb > 1 ? bbp::stage_first(c.bb, L.tw) : bbp::Stage{};
+    for (int s = 0; s < ws.nstages && !rc; ++s, sg = s < ws.nstages ? bbp::stage_next(sg, L.tw) : sg) {
         bbk::StageArgs a;
         a.W = W;
         a.S = ws.ldw - 1;
@@ -456,8 +500,7 @@ static int reduce_impl(int64_t n, int64_t b, int dtype, const void* band, int64_
         a.nxcd = ds->nxcd > 1 && L.xcd_run > 0 ? ds->nxcd : 0;
         a.xcd_run = std::max(L.xcd_run, 1);
         if (a.nsweeps == 0) continue;
-        if (dtype == BB_F16)
-            rc = check_hip(bbk::launch_f16_rescale(W, n * ws.ldw, f16_amax + s, f16_exps, s, st));
+        if (dtype == BB_F16) rc = check_hip(bbk::launch_f16_rescale(W, n * ws.ldw, f16_amax + s, f16_exps, s, st));
         if (rc) break;
         const int twm = bbp::kernel_twm(sg.tw);
         int ntl_s = 0, lanes_s = 0;
@@ -466,15 +509,22 @@ static int reduce_impl(int64_t n, int64_t b, int dtype, const void* band, int64_
         const int grid = (int)std::min<int64_t>(ngroups, (int64_t)ds->cus * L.groups_per_cu);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         bool timed = false;
-        {
+        if (timing_allowed) {
             std::lock_guard<std::mutex> lk(g_mu);
             timed = g_timing.on;
         }
-        if (timed && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess)
-            hipEventRecord(e0, st);
+        if (timed) {
+            if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+                if (e0) (void)hipEventDestroy(e0);
+                e0 = e1 = nullptr;
+                timed = false;
+            } else {
+                (void)hipEventRecord(e0, st);
+            }
+        }
         rc = check_hip(bbk::launch_stage(dtype, a, twm, ntl_s, lanes_s, grid, st));
-        if (timed && e1) {
-            hipEventRecord(e1, st);
+        if (timed) {
+            (void)hipEventRecord(e1, st);
             std::lock_guard<std::mutex> lk(g_mu);
             g_timing.events.emplace_back(e0, e1);
         }
@@ -484,9 +534,22 @@ static int reduce_impl(int64_t n, int64_t b, int dtype, const void* band, int64_
             // every stage has n - c - 1 >= 1 sweeps (c <= b - 1 <= n - 2), so each one rescaled
             rc = check_hip(bbk::launch_extract_f16(W, n, ws.ldw, ws.uo, f16_exps, ws.nstages, d, e, st));
         } else {
-            rc = check_hip(bbk::launch_extract(dtype, W, n, ws.ldw, ws.uo, inv_scale, d, e, st));
+            rc = check_hip(bbk::launch_extract(dtype, W, n, ws.ldw, ws.uo, 1.0, d, e, st));
         }
     }
+    return rc;
+}
+
+// Body of bb_reduce for validated arguments, with explicit parameters: working
+// memory from the device's stream-ordered pool.
+static int reduce_impl(int64_t n, int64_t b, int dtype, const void* band, int64_t ldband, double* d, double* e,
+                       hipStream_t st, DeviceState* ds, const bb_params_t& params, bool use_cache) {
+    Call c;
+    int rc = prepare_call(n, b, dtype, ds, params, use_cache, &c);
+    if (rc) return rc;
+    void* base = nullptr;
+    if (hipMallocAsync(&base, c.ws.total, st) != hipSuccess) return BB_ERR_NOMEM;
+    rc = enqueue_call(c, band, ldband, d, e, st, ds, static_cast<char*>(base), true);
     hipError_t fe = hipFreeAsync(base, st);
     if (!rc && fe != hipSuccess) rc = BB_ERR_HIP;
     return rc;
@@ -596,8 +659,7 @@ int bb_stream_status(void* stream) {
     int rc = device_state(&ds);
     if (rc) return rc;
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return BB_ERR_HIP;
-    int v = __atomic_exchange_n(ds->err_host, 0, __ATOMIC_SEQ_CST);
-    return v;
+    return read_err_word(ds, true);
 }
 
 int bb_timing_enable(int on) {
@@ -731,7 +793,7 @@ extern "C" int bb_autotune(int64_t n, int64_t b, bb_dtype_t dtype, void* stream,
         if (!rc) rc = check_hip(hipEventSynchronize(e1));
         float ms = 0.f;
         if (!rc) rc = check_hip(hipEventElapsedTime(&ms, e0, e1));
-        if (!rc && __atomic_load_n(ds->err_host, __ATOMIC_SEQ_CST)) rc = BB_ERR_TIMEOUT;
+        if (!rc && read_err_word(ds, false)) rc = BB_ERR_TIMEOUT;
         if (!rc && ms < best_ms) {
             best_ms = ms;
             best = c;

@@ -10,14 +10,27 @@ namespace bbp {
 
 int min_lag(int c) { return c >= 3 ? 2 : (c == 2 ? 3 : 4); }
 
+Stage stage_first(int64_t b, int tw) {
+    const int t = (int)std::min<int64_t>(tw, b - 1);
+    const int c = (int)(b - t);
+    return Stage{(int)b, t, c, min_lag(c)};
+}
+
+Stage stage_next(const Stage& s, int tw) { return stage_first(s.c, tw); }
+
+int stage_count(int64_t b, int tw) {
+    int k = 0;
+    for (int64_t x = b; x > 1; x -= std::min<int64_t>(tw, x - 1)) ++k;
+    return k;
+}
+
 Plan make_plan(int64_t b, int tw) {
     Plan p;
-    while (b > 1) {
-        int t = (int)std::min<int64_t>(tw, b - 1);
-        int c = (int)(b - t);
-        p.stages.push_back(Stage{(int)b, t, c, min_lag(c)});
-        b = c;
-    }
+    if (b > 1)
+        for (Stage s = stage_first(b, tw);; s = stage_next(s, tw)) {
+            p.stages.push_back(s);
+            if (s.c <= 1) break;
+        }
     return p;
 }
 

@@ -26,6 +26,12 @@ struct Plan {
 
 // Stages of Algorithm 1's outer loop: reduce by TW until the band is bidiagonal.
 Plan make_plan(int64_t b, int tw);
+// The same stages one at a time, without building a Plan: stage_first(b, tw) is
+// the first stage (valid iff b > 1), stage_next(s, tw) the one after s (valid
+// iff s.c > 1).
+Stage stage_first(int64_t b, int tw);
+Stage stage_next(const Stage& s, int tw);
+int stage_count(int64_t b, int tw);
 // Smallest half-step lag H for which concurrently running tasks of consecutive
 // sweeps are disjoint (see bb_kernels.hip): 2 for c >= 3, 3 for c = 2, 4 for c = 1.
 int min_lag(int c);

@@ -248,3 +248,46 @@ def test_nrm2_safe_scaling_matches_definition(scale):
     mixed = [1e-310, 3.0, 1e-200, 4.0] if scale == 1.0 else [scale, 1e-320, 2.0 * scale]
     ref = math.sqrt(sum((v / max(mixed)) ** 2 for v in mixed)) * max(mixed)
     assert abs(oracle._nrm2(mixed) - ref) <= 8 * EPS * ref
+
+
+_NRM2_CASES = [
+    [3.0, 4.0],                                   # mid range only
+    [2.0 ** 600, 2.0 ** 600, -(2.0 ** 601)],      # huge only (abig accumulator)
+    [2.0 ** 487, 2.0 ** 486],                     # huge + mid at the tbig threshold
+    [2.0 ** 700, 1.0, -3.0, 2.0 ** 699],          # huge + mid combined
+    [2.0 ** 700, 1e-300, 5e-324],                 # huge + tiny (tiny ignored)
+    [1e-300, -2e-300, 3e-310],                    # tiny only (asml accumulator)
+    [1e-300, 3.0, 1e-200, 4.0],                   # tiny + mid combined
+    [2.0 ** -511, 2.0 ** -512],                   # tiny / mid threshold
+    [0.0, 0.0, 2.0 ** 1000, 0.0],                 # zeros and one huge value
+    [1.0e308, -1.0e308],                          # overflows as a plain sum of squares
+]
+
+
+@pytest.mark.parametrize("x", _NRM2_CASES)
+def test_c_nrm2_every_regime(x):
+    """The C oracle's xNRM2 itself (not only its Python twin): the Euclidean norm
+    within 2 ulp (Python's math.hypot of many arguments is the reference) in every
+    accumulator regime, and bitwise equal to the independent Python coding."""
+    ref = math.hypot(*x)
+    got = oracle.nrm2(np.array(x))
+    assert abs(got - ref) <= 2 * EPS * ref, (got, ref)
+    assert got == oracle._nrm2(x)
+
+
+@pytest.mark.parametrize("n,b,tw", [(30, 6, 2), (40, 9, 4), (24, 12, 11)])
+def test_huge_scaling_takes_the_big_accumulator_exactly(n, b, tw):
+    """Scaling A by 2^600 puts every nonzero entry above xNRM2's 2^486 threshold, so
+    every norm goes through the huge-value accumulator (scaled by 2^-538) of the C
+    oracle.  A power of two commutes with each operation, so d and e must scale
+    exactly, and the band oracle must equal the dense full-range chase (whose norm is
+    the separate Python coding) bit for bit."""
+    band = _well_conditioned_band(n, b, seed=78)
+    d0, e0 = oracle.reduce(band, n, b, tw)
+    s = 2.0 ** 600
+    d1, e1 = oracle.reduce(band * s, n, b, tw)
+    assert np.isfinite(d1).all() and np.isfinite(e1).all()
+    assert np.array_equal(d1, d0 * s) and np.array_equal(e1, e0 * s)
+    A = band_to_dense(band * s, n, b)
+    M = np.array(oracle.reduce_dense_full(A.tolist(), b, tw))
+    assert np.array_equal(d1, np.diag(M)) and np.array_equal(e1, np.diag(M, 1))
