@@ -56,7 +56,9 @@ enum {
                                 column height whose in-window byte offsets would exceed
                                 32 bits (working-band columns above about 5.4 million FP64
                                 entries; b is far smaller at any size that fits) */
-    BB_ERR_NODEVICE = 5      /* no usable gfx950 device */
+    BB_ERR_NODEVICE = 5,     /* no usable gfx950 device */
+    BB_ERR_SCRATCH = 6       /* bb_reduce_noalloc: the call's working memory exceeds the
+                                library's static scratch (64 MiB per device) */
 };
 
 /*
@@ -106,6 +108,27 @@ typedef struct {
  */
 int bb_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void *band, int64_t ldband,
               double *d, double *e, void *stream);
+
+/*
+ * bb_reduce for callers that cannot allocate device memory: code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
+ * argument numbers, launch parameters and results as bb_reduce (bitwise: the
+ * same kernels run in the same configuration); the difference is where the
+ * working memory lives.  It is a static device array of 64 MiB that the library
+ * holds on every device it runs on until the process ends; this call allocates
+ * nothing (no hipMalloc / hipMallocAsync / hipFree, no events) and clears the
+ * counters it needs with a kernel at the start of each call.
+ *   Limit: the working memory of the call, bb_workspace_bytes(n, b, dtype), must
+ *   be at most 64 MiB (it is about 51 MiB for n = 32768, b = 128 in FP64; it
+ *   grows with n (b + 2 TW + 1) times the element size); larger shapes return
+ *   BB_ERR_SCRATCH with no work enqueued.
+ *   Concurrency: every call on one device shares that device's scratch, so calls
+ *   that overlap in time on one device (e.g. on two streams) race and give wrong
+ *   results; issue them on one stream or otherwise serialise them.  Calls of
+ *   bb_reduce and bb_reduce_batched use their own memory and do not conflict.
+ */
+int bb_reduce_noalloc(int64_t n, int64_t b, bb_dtype_t dtype, const void *band, int64_t ldband,
+                      double *d, double *e, void *stream);
 
 /*
  * Reduce `count` independent bands of uneven n_i, b_i in one persistent launch

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_PKG, "lib", "libbb.so")
 
 F64, F32, F16 = 0, 1, 2
 _ERRNAMES = {1: "BB_ERR_HIP", 2: "BB_ERR_TIMEOUT", 3: "BB_ERR_NOMEM", 4: "BB_ERR_UNSUPPORTED",
-             5: "BB_ERR_NODEVICE"}
+             5: "BB_ERR_NODEVICE", 6: "BB_ERR_SCRATCH"}
 
 
 class BBError(RuntimeError):
@@ -47,6 +47,8 @@ def _load():
     i64, vp, dp, ip = ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
     lib.bb_reduce.argtypes = [i64, i64, ctypes.c_int, vp, i64, vp, vp, vp]
     lib.bb_reduce.restype = ctypes.c_int
+    lib.bb_reduce_noalloc.argtypes = [i64, i64, ctypes.c_int, vp, i64, vp, vp, vp]
+    lib.bb_reduce_noalloc.restype = ctypes.c_int
     lib.bb_reduce_batched.argtypes = [i64, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.c_int,
                                       ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(vp),
                                       ctypes.POINTER(vp), vp]
@@ -84,7 +86,7 @@ def _load():
 
 lib = _load()
 
-EXPORTS = ("bb_reduce", "bb_reduce_batched", "bb_set_params", "bb_get_params", "bb_autotune", "bb_resolved_params",
+EXPORTS = ("bb_reduce", "bb_reduce_noalloc", "bb_reduce_batched", "bb_set_params", "bb_get_params", "bb_autotune", "bb_resolved_params",
            "bb_workspace_bytes", "bb_model_bytes", "bb_plan", "bb_min_lag", "bb_stream_status",
            "bb_release", "bb_error_string", "bb_timing_enable", "bb_timing_read", "bb_bidiag_sigma")
 
@@ -125,6 +127,21 @@ def bb_reduce(band, n: int, b: int, d=None, e=None, stream=None, ldband: int | N
     rc = lib.bb_reduce(n, b, _torch_dtype_code(band), ctypes.c_void_p(band.data_ptr()), ld,
                        ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(e.data_ptr()), _stream_handle(stream))
     _check(rc, "bb_reduce")
+    return d[:n], e[:max(n - 1, 0)]
+
+
+def bb_reduce_noalloc(band, n: int, b: int, d, e, stream=None, ldband: int | None = None):
+    """bb_reduce through the allocation-free entry point: the library works in its
+    static per-device scratch.  ``d`` and ``e`` are caller-provided float64 device
+    tensors (n and max(n - 1, 1) entries); returns views of them."""
+    if not band.is_cuda:
+        raise ValueError("band must be a device tensor")
+    if not band.is_contiguous():
+        raise ValueError("band must be contiguous (n, ldband)")
+    ld = ldband if ldband is not None else (band.shape[1] if band.dim() == 2 else b + 1)
+    rc = lib.bb_reduce_noalloc(n, b, _torch_dtype_code(band), ctypes.c_void_p(band.data_ptr()), ld,
+                               ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(e.data_ptr()), _stream_handle(stream))
+    _check(rc, "bb_reduce_noalloc")
     return d[:n], e[:max(n - 1, 0)]
 
 

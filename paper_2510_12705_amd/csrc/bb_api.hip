@@ -25,12 +25,25 @@ constexpr int kMaxXcd = 16;  // per-XCD claim counters kept per stage
 // bb_stream_status.  A device global, so that setting up a device allocates nothing.
 __device__ int g_err_word;
 
+}  // namespace
+
+// Working memory of bb_reduce_noalloc: one call's working band and dependency
+// counters, in a static device array that every device holding the library keeps
+// until the process ends.  Host code never passes this name to a kernel or a
+// copy: it is a host-side stand-in for the symbol, and device_state() resolves
+// each device's own address of it with hipGetSymbolAddress.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
 struct DeviceState {
     bool init = false;
     int cus = 0;
     size_t lds_per_block = 65536;  // largest dynamic LDS allocation of one workgroup
     int nxcd = 1;                  // XCDs (accelerator complex dies), each with its own L2
     int* err_dev = nullptr;        // this device's copy of g_err_word
+    char* scratch_dev = nullptr;   // this device's copy of `scratch` (bb_reduce_noalloc)
 };
 
 std::mutex g_mu;
@@ -67,6 +80,7 @@ int device_state(DeviceState** out) {
         if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, dev) == hipSuccess && nx >= 1)
             s.nxcd = std::min(nx, (int)kMaxXcd);
         if (hipGetSymbolAddress((void**)&s.err_dev, HIP_SYMBOL(g_err_word)) != hipSuccess) return BB_ERR_HIP;
+        if (hipGetSymbolAddress((void**)&s.scratch_dev, HIP_SYMBOL(scratch)) != hipSuccess) return BB_ERR_HIP;
         hipMemPool_t pool;
         if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
             uint64_t thr = UINT64_MAX;  // keep freed working memory cached in the pool
@@ -555,6 +569,30 @@ static int reduce_impl(int64_t n, int64_t b, int dtype, const void* band, int64_
     return rc;
 }
 
+// bb_reduce with the device's static scratch as working memory: the same launch
+// sequence (counters cleared by a fill kernel, pack, stages, extract), no device
+// allocation and no timing events.
+int bb_reduce_noalloc(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, int64_t ldband, double* d, double* e,
+                      void* stream) {
+    if (n < 0) return -1;
+    if (b < 0) return -2;
+    if (dtype != BB_F64 && dtype != BB_F32 && dtype != BB_F16) return -3;
+    if (n > 0 && !band) return -4;
+    if (ldband < b + 1) return -5;
+    if (n > 0 && !d) return -6;
+    if (n > 1 && !e) return -7;
+    if (n > (int64_t)1 << 30) return -1;
+    if (n == 0) return BB_OK;
+    DeviceState* ds = nullptr;
+    int rc = device_state(&ds);
+    if (rc) return rc;
+    Call c;
+    rc = prepare_call(n, b, dtype, ds, current_params(), true, &c);
+    if (rc) return rc;
+    if (c.ws.total > kScratchBytes) return BB_ERR_SCRATCH;
+    return enqueue_call(c, band, ldband, d, e, (hipStream_t)stream, ds, ds->scratch_dev, false);
+}
+
 int bb_reduce_batched(int64_t count, const int64_t* n, const int64_t* b, bb_dtype_t dtype, const void* const* band,
                       const int64_t* ldband, double* const* d, double* const* e, void* stream) {
     if (count < 0 || count > (1 << 20)) return -1;
@@ -704,6 +742,7 @@ const char* bb_error_string(int code) {
         case BB_ERR_NOMEM: return "out of memory";
         case BB_ERR_UNSUPPORTED: return "unsupported parameters";
         case BB_ERR_NODEVICE: return "no usable device";
+        case BB_ERR_SCRATCH: return "working memory exceeds the 64 MiB static scratch of bb_reduce_noalloc";
         default: return "unknown error";
     }
 }

@@ -46,6 +46,15 @@ def test_argument_validation_without_device():
     assert L.bb_reduce(8, 4, 0, dummy, 5, None, dummy, None) == -6
     assert L.bb_reduce(8, 4, 0, dummy, 5, dummy, None, None) == -7
     assert L.bb_reduce(0, 4, 0, None, 5, None, None, None) == 0     # n = 0 is a no-op
+    # the allocation-free entry point validates the same arguments the same way
+    assert L.bb_reduce_noalloc(-1, 4, 0, dummy, 5, dummy, dummy, None) == -1
+    assert L.bb_reduce_noalloc(8, -1, 0, dummy, 5, dummy, dummy, None) == -2
+    assert L.bb_reduce_noalloc(8, 4, 7, dummy, 5, dummy, dummy, None) == -3
+    assert L.bb_reduce_noalloc(8, 4, 0, None, 5, dummy, dummy, None) == -4
+    assert L.bb_reduce_noalloc(8, 4, 0, dummy, 4, dummy, dummy, None) == -5
+    assert L.bb_reduce_noalloc(8, 4, 0, dummy, 5, None, dummy, None) == -6
+    assert L.bb_reduce_noalloc(8, 4, 0, dummy, 5, dummy, None, None) == -7
+    assert L.bb_reduce_noalloc(0, 4, 0, None, 5, None, None, None) == 0
     I64 = ctypes.c_int64 * 1
     VP = ctypes.c_void_p * 1
     assert L.bb_reduce_batched(-1, None, None, 0, None, None, None, None, None) == -1
