@@ -65,13 +65,16 @@ enum {
  * Tuning parameters (Sec. III-C names three knobs: threads per block, inner
  * tilewidth, maximum blocks).  0 in any field means "automatic".
  *   tw                 inner tilewidth TW (entries annihilated per reflector);
- *                      supported values: 1..32.
- *   threads_per_window threads that work on one sweep's window: 64, 128 or 256.
+ *                      supported values: 1..32 for BB_F64, 1..64 for BB_F32 and
+ *                      BB_F16 (a call with a larger value returns
+ *                      BB_ERR_UNSUPPORTED).
+ *   threads_per_window threads that work on one sweep's window: 64, 128 or 256
+ *                      (a stage with tw > 32 uses at least 128).
  *   sweeps_per_group   consecutive sweeps one workgroup advances in lock-step
  *                      (1..16, threads_per_window * sweeps_per_group <= 1024);
  *                      hand-over inside a group costs one workgroup barrier.
  *                      A stage whose kernel variant accepts fewer threads per
- *                      workgroup (256 for tw 17..32, 512 for 9..16) runs fewer
+ *                      workgroup (256 for tw 17..64, 512 for 9..16) runs fewer
  *                      sweeps per group; results do not depend on it.
  *   groups_per_cu      persistent workgroups launched per compute unit (1..16;
  *                      automatic: 2 for bb_reduce, 4 for bb_reduce_batched);
@@ -180,15 +183,35 @@ int bb_get_params(bb_params_t *p);
  * work (Sec. VII); this is that search, ranked by a model and judged by time.
  * A short list of parameter sets (the built-in
  * defaults and shapes that win in other regimes; fields fixed by bb_set_params
- * are kept in all of them) is ranked by a critical-path model, the best six are
- * timed on a synthetic band of this shape (n capped at 32768) on `stream`, and
- * the fastest is cached for (floor(log2 n), min(b, n-1), dtype).  Later calls of
+ * are kept in all of them) is ranked by a critical-path model; the defaults and
+ * the best five others are each timed three times (after one untimed run) on a
+ * synthetic band of this shape (n capped at 32768) on `stream`, the median
+ * decides, and the winner -- the defaults unless another set is at least 1 %
+ * faster -- is cached for (floor(log2 n), min(b, n-1), dtype).  Later calls of
  * bb_reduce for that key use the cached fields that bb_set_params leaves at 0.
  * *out (may be NULL) receives the first-stage launch shape of the winner.
  * Allocates stream-ordered device memory and synchronises `stream`.
  * bb_release() clears the cache.
  */
 int bb_autotune(int64_t n, int64_t b, bb_dtype_t dtype, void *stream, bb_params_t *out);
+
+/*
+ * Autotune the batched form for one exact batch (count, n[], b[], dtype; host
+ * arrays as in bb_reduce_batched).  The same search as bb_autotune (Sec. III-C
+ * knobs, Sec. VII's automatic tuning), over the batched form's candidates
+ * (workgroups per CU, tilewidth, threads per window, sweeps per group): each is
+ * timed three times on synthetic bands of exactly these shapes and the median
+ * decides; the defaults stay unless a candidate is at least 1 % faster.  The
+ * winner is cached for this exact batch and used by later bb_reduce_batched
+ * calls with the same (count, n[], b[], dtype) for the fields bb_set_params
+ * leaves at 0.  The winner's batch plan (and its workspace) is kept, so the next
+ * call with the batch allocates nothing and may be captured into a hipGraph.
+ * *out (may be NULL) receives the winner's launch shape.  Allocates stream-ordered
+ * device memory and synchronises `stream`.  Argument numbers: count=1, n=2, b=3,
+ * dtype=4.  bb_release() clears the cache.
+ */
+int bb_autotune_batched(int64_t count, const int64_t *n, const int64_t *b, bb_dtype_t dtype,
+                        void *stream, bb_params_t *out);
 
 /* The parameters (first-stage launch shape) bb_reduce would use for this shape
  * now: bb_set_params fields, then an autotuned entry, then the defaults.  Host

@@ -59,6 +59,9 @@ def _load():
     lib.bb_get_params.restype = ctypes.c_int
     lib.bb_autotune.argtypes = [i64, i64, ctypes.c_int, vp, ctypes.POINTER(Params)]
     lib.bb_autotune.restype = ctypes.c_int
+    lib.bb_autotune_batched.argtypes = [i64, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.c_int, vp,
+                                        ctypes.POINTER(Params)]
+    lib.bb_autotune_batched.restype = ctypes.c_int
     lib.bb_resolved_params.argtypes = [i64, i64, ctypes.c_int, ctypes.POINTER(Params)]
     lib.bb_resolved_params.restype = ctypes.c_int
     lib.bb_workspace_bytes.argtypes = [i64, i64, ctypes.c_int]
@@ -86,7 +89,7 @@ def _load():
 
 lib = _load()
 
-EXPORTS = ("bb_reduce", "bb_reduce_noalloc", "bb_reduce_batched", "bb_set_params", "bb_get_params", "bb_autotune", "bb_resolved_params",
+EXPORTS = ("bb_reduce", "bb_reduce_noalloc", "bb_reduce_batched", "bb_set_params", "bb_get_params", "bb_autotune", "bb_autotune_batched", "bb_resolved_params",
            "bb_workspace_bytes", "bb_model_bytes", "bb_plan", "bb_min_lag", "bb_stream_status",
            "bb_release", "bb_error_string", "bb_timing_enable", "bb_timing_read", "bb_bidiag_sigma")
 
@@ -198,6 +201,16 @@ def get_params() -> Params:
 def autotune(n: int, b: int, dtype: int, stream=None) -> Params:
     p = Params()
     _check(lib.bb_autotune(n, b, dtype, _stream_handle(stream), ctypes.byref(p)), "bb_autotune")
+    return p
+
+
+def autotune_batched(ns, bs, dtype: int, stream=None) -> Params:
+    """Tune the batched form for this exact batch of shapes (see bb.h)."""
+    count = len(ns)
+    I64 = ctypes.c_int64 * max(count, 1)
+    p = Params()
+    _check(lib.bb_autotune_batched(count, I64(*ns), I64(*bs), dtype, _stream_handle(stream), ctypes.byref(p)),
+           "bb_autotune_batched")
     return p
 
 

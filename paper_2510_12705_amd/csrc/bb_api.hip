@@ -138,8 +138,10 @@ Launch resolve(int64_t n, int64_t b, int dtype, size_t lds_limit, bb_params_t p,
     L.groups_per_cu = p.groups_per_cu ? p.groups_per_cu : default_groups_per_cu;
     L.lag = p.lag;
     L.xcd_run = p.xcd_run ? p.xcd_run : 2;
-    // fit the workgroup's LDS (corners + staging blocks) and thread limits
+    // fit the workgroup's LDS (corners + staging blocks) and thread limits; a
+    // 64-wide tile writes 65-entry segments, one thread per entry
     const int twm = bbp::kernel_twm(L.tw);
+    if (twm > 32 && L.ntl < 128) L.ntl = 128;
     while (L.lanes > 1 && bbk::stage_lds_bytes(dtype, twm, L.ntl, L.lanes) > lds_limit) --L.lanes;
     while (L.lanes > 1 && L.lanes * L.ntl > bbk::stage_max_threads(twm)) --L.lanes;
     return L;
@@ -149,6 +151,7 @@ Launch resolve(int64_t n, int64_t b, int dtype, size_t lds_limit, bb_params_t p,
 void stage_shape(const Launch& L, const bbp::Stage& sg, int dtype, int* ntl, int* lanes) {
     const int twm = bbp::kernel_twm(sg.tw);
     int nt = L.ntl_fixed ? L.ntl : bbp::default_threads(sg.b + sg.tw, dtype);
+    if (twm > 32 && nt < 128) nt = 128;
     int ln = L.lanes_fixed ? L.lanes : bbp::default_lanes(nt, dtype);
     while (ln > 1 && bbk::stage_lds_bytes(dtype, twm, nt, ln) > L.lds_limit) --ln;
     while (ln > 1 && ln * nt > bbk::stage_max_threads(twm)) --ln;
@@ -239,6 +242,39 @@ struct BatchPlan {
 };
 
 std::vector<BatchPlan*> g_batch_plans;
+
+// Tuned parameters of the batched form, keyed on the exact batch (dtype, n[], b[]).
+struct BatchTuned {
+    int dtype;
+    std::vector<int64_t> ns, bs;
+    bb_params_t p;
+};
+std::vector<BatchTuned> g_batch_tuned;
+
+bool batch_tuned_lookup(int64_t count, const int64_t* n, const int64_t* b, int dtype, bb_params_t* p) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (const BatchTuned& t : g_batch_tuned) {
+        if (t.dtype != dtype || (int64_t)t.ns.size() != count) continue;
+        if (std::equal(t.ns.begin(), t.ns.end(), n) && std::equal(t.bs.begin(), t.bs.end(), b)) {
+            *p = t.p;
+            return true;
+        }
+    }
+    return false;
+}
+
+void batch_tuned_store(int64_t count, const int64_t* n, const int64_t* b, int dtype, const bb_params_t& p) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (BatchTuned& t : g_batch_tuned)
+        if (t.dtype == dtype && (int64_t)t.ns.size() == count && std::equal(t.ns.begin(), t.ns.end(), n) &&
+            std::equal(t.bs.begin(), t.bs.end(), b)) {
+            t.p = p;
+            return;
+        }
+    g_batch_tuned.push_back(BatchTuned{dtype, std::vector<int64_t>(n, n + count), std::vector<int64_t>(b, b + count), p});
+}
+
+
 
 uint64_t mix(uint64_t h, uint64_t v) {
     h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
@@ -472,7 +508,7 @@ static int prepare_call(int64_t n, int64_t b, int dtype, DeviceState* ds, const 
     c->bb = std::min<int64_t>(b, n - 1);
     c->dtype = dtype;
     c->L = resolve(n, c->bb, dtype, ds->lds_per_block, params, use_cache);
-    if (c->L.tw < 1 || c->L.tw > bbp::kMaxTW) return BB_ERR_UNSUPPORTED;
+    if (c->L.tw < 1 || c->L.tw > bbp::max_tw(dtype)) return BB_ERR_UNSUPPORTED;
     c->ws = workspace_layout(n, c->bb, dtype, c->L.tw);
     if (!window_offsets_fit(c->ws, dtype)) return BB_ERR_UNSUPPORTED;
     return BB_OK;
@@ -617,8 +653,20 @@ int bb_reduce_batched(int64_t count, const int64_t* n, const int64_t* b, bb_dtyp
         max_n = std::max(max_n, n[i]);
         max_b = std::max(max_b, std::min(b[i], std::max<int64_t>(n[i] - 1, 0)));
     }
-    Launch L = resolve(max_n, max_b, dtype, ds->lds_per_block, current_params(), true, 4);
-    if (L.tw < 1 || L.tw > bbp::kMaxTW) return BB_ERR_UNSUPPORTED;
+    // a nonzero bb_set_params field wins, then a bb_autotune_batched entry for this
+    // exact batch, then the batched defaults
+    bb_params_t prm = current_params();
+    bb_params_t tuned;
+    if (batch_tuned_lookup(count, n, b, dtype, &tuned)) {
+        if (!prm.tw) prm.tw = tuned.tw;
+        if (!prm.threads_per_window) prm.threads_per_window = tuned.threads_per_window;
+        if (!prm.sweeps_per_group) prm.sweeps_per_group = tuned.sweeps_per_group;
+        if (!prm.groups_per_cu) prm.groups_per_cu = tuned.groups_per_cu;
+        if (!prm.lag) prm.lag = tuned.lag;
+        if (!prm.xcd_run) prm.xcd_run = tuned.xcd_run;
+    }
+    Launch L = resolve(max_n, max_b, dtype, ds->lds_per_block, prm, false, 4);
+    if (L.tw < 1 || L.tw > bbp::max_tw(dtype)) return BB_ERR_UNSUPPORTED;
     BatchPlan* bp = nullptr;
     rc = batch_plan(count, n, b, dtype, L, st, &bp);
     if (rc) return rc;
@@ -729,6 +777,10 @@ int bb_timing_read(double* stage_ms, int64_t* stage_launches) {
 
 int bb_release(void) {
     bbp::autotune_clear();
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_batch_tuned.clear();
+    }
     batch_plans_clear();
     return BB_OK;
 }
@@ -758,6 +810,91 @@ static double model_time(int64_t n, int64_t b, int elem, int tw) {
     return t;
 }
 
+namespace {
+
+constexpr int kTuneReps = 3;          // timed runs per candidate (the median decides)
+constexpr float kTuneMargin = 0.99f;  // a candidate replaces the defaults only if at least 1 % faster
+
+// Candidate launch parameters: the built-in defaults first, then shapes that win
+// in some regime.  Fields fixed by bb_set_params hold for every candidate.
+std::vector<bb_params_t> tune_candidates(int dtype, bool batched, const bb_params_t& user) {
+    const int tw_alt = dtype == BB_F64 ? 16 : 64;
+    std::vector<bb_params_t> c;
+    if (!batched)
+        c = {{0, 0, 0, 0, 0, 0},      {tw_alt, 0, 0, 0, 0, 0}, {0, 0, 0, 1, 0, 0}, {0, 0, 0, 3, 0, 0},
+             {0, 0, 0, 0, 0, 1},      {0, 0, 0, 0, 0, 8},      {0, 0, 2, 0, 0, 0}, {0, 128, 1, 2, 0, 0}};
+    else
+        c = {{0, 0, 0, 0, 0, 0}, {tw_alt, 0, 0, 0, 0, 0}, {0, 0, 0, 2, 0, 0}, {0, 0, 0, 3, 0, 0},
+             {tw_alt, 0, 0, 3, 0, 0}, {0, 128, 0, 0, 0, 0}, {0, 0, 2, 2, 0, 0}};
+    std::vector<bb_params_t> out;
+    for (bb_params_t x : c) {
+        if (user.tw) x.tw = user.tw;
+        if (user.threads_per_window) x.threads_per_window = user.threads_per_window;
+        if (user.sweeps_per_group) x.sweeps_per_group = user.sweeps_per_group;
+        if (user.groups_per_cu) x.groups_per_cu = user.groups_per_cu;
+        if (user.lag) x.lag = user.lag;
+        if (user.xcd_run) x.xcd_run = user.xcd_run;
+        if (x.tw > bbp::max_tw(dtype)) continue;
+        bool dup = false;
+        for (const bb_params_t& y : out)
+            if (!std::memcmp(&x, &y, sizeof(x))) dup = true;
+        if (!dup) out.push_back(x);
+    }
+    return out;
+}
+
+// Time `run` (which enqueues one call on st) kReps times after one untimed run;
+// *ms receives the median.
+template <typename Run>
+int time_median(Run&& run, hipStream_t st, DeviceState* ds, hipEvent_t e0, hipEvent_t e1, float* ms) {
+    int rc = run();
+    if (!rc) rc = check_hip(hipStreamSynchronize(st));
+    float t[kTuneReps];
+    for (int i = 0; i < kTuneReps && !rc; ++i) {
+        rc = check_hip(hipEventRecord(e0, st));
+        if (!rc) rc = run();
+        if (!rc) rc = check_hip(hipEventRecord(e1, st));
+        if (!rc) rc = check_hip(hipEventSynchronize(e1));
+        if (!rc) rc = check_hip(hipEventElapsedTime(&t[i], e0, e1));
+    }
+    if (!rc && read_err_word(ds, false)) rc = BB_ERR_TIMEOUT;
+    if (rc) return rc;
+    std::sort(t, t + kTuneReps);
+    *ms = t[kTuneReps / 2];
+    return BB_OK;
+}
+
+// Pick among timed candidates: the fastest median, unless it is not at least
+// 1 % faster than the defaults (candidate 0), which then stay.
+size_t pick_winner(const std::vector<float>& ms) {
+    size_t best = 0;
+    for (size_t i = 1; i < ms.size(); ++i)
+        if (ms[i] < ms[best]) best = i;
+    return ms[best] <= kTuneMargin * ms[0] ? best : 0;
+}
+
+// Free batch plans made after index `from` whose launch does not match `keep`.
+void batch_plans_drop_after(size_t from, const BatchPlan* keep) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    std::vector<BatchPlan*> kept(g_batch_plans.begin(), g_batch_plans.begin() + std::min(from, g_batch_plans.size()));
+    for (size_t i = from; i < g_batch_plans.size(); ++i) {
+        BatchPlan* p = g_batch_plans[i];
+        if (p == keep) {
+            kept.push_back(p);
+            continue;
+        }
+        if (p->staged_pending) (void)hipEventSynchronize(p->staged);
+        (void)hipEventDestroy(p->staged);
+        (void)hipHostFree(p->pinned);
+        (void)hipHostFree(p->pinned_capture);
+        (void)hipFree(p->dev);
+        delete p;
+    }
+    g_batch_plans.swap(kept);
+}
+
+}  // namespace
+
 extern "C" int bb_autotune(int64_t n, int64_t b, bb_dtype_t dtype, void* stream, bb_params_t* out) {
     if (n < 0) return -1;
     if (b < 0) return -2;
@@ -776,36 +913,18 @@ extern "C" int bb_autotune(int64_t n, int64_t b, bb_dtype_t dtype, void* stream,
         report(user);
         return BB_OK;
     }
-    // candidates: the built-in defaults and the shapes that win in some regime;
-    // fields fixed by bb_set_params hold for every candidate
-    std::vector<bb_params_t> cands = {{0, 0, 0, 0, 0, 0},   {0, 256, 1, 1, 0, 0}, {0, 0, 0, 1, 0, 0},
-                                      {16, 0, 0, 0, 0, 0},  {0, 0, 2, 0, 0, 0},   {0, 0, 0, 0, 0, 8},
-                                      {0, 128, 1, 2, 0, 0}, {8, 0, 0, 0, 0, 0}};
-    for (bb_params_t& c : cands) {
-        if (user.tw) c.tw = user.tw;
-        if (user.threads_per_window) c.threads_per_window = user.threads_per_window;
-        if (user.sweeps_per_group) c.sweeps_per_group = user.sweeps_per_group;
-        if (user.groups_per_cu) c.groups_per_cu = user.groups_per_cu;
-        if (user.lag) c.lag = user.lag;
-        if (user.xcd_run) c.xcd_run = user.xcd_run;
-    }
     const int64_t nt = std::min<int64_t>(n, 32768);
     const int64_t bt = std::min<int64_t>(bb, nt - 1);
     const int elem = (int)elem_size(dtype);
-    std::vector<std::pair<double, bb_params_t>> ranked;
-    for (const bb_params_t& c : cands) {
-        bool dup = false;
-        for (auto& r : ranked)
-            if (!std::memcmp(&r.second, &c, sizeof(c))) dup = true;
-        if (dup) continue;
+    // rank by the critical-path model; the defaults (first) are always timed
+    std::vector<bb_params_t> cands = tune_candidates(dtype, false, user);
+    auto model = [&](const bb_params_t& c) {
         const int tw = c.tw ? c.tw : bbp::default_tw(dtype);
-        ranked.emplace_back(model_time(nt, bt, elem, std::min<int64_t>(tw, std::max<int64_t>(bt - 1, 1))), c);
-    }
-    std::stable_sort(ranked.begin(), ranked.end(),
-                     [](const std::pair<double, bb_params_t>& x, const std::pair<double, bb_params_t>& y) {
-                         return x.first < y.first * 0.999;
-                     });
-    if (ranked.size() > 6) ranked.resize(6);
+        return model_time(nt, bt, elem, (int)std::min<int64_t>(tw, std::max<int64_t>(bt - 1, 1)));
+    };
+    std::stable_sort(cands.begin() + 1, cands.end(),
+                     [&](const bb_params_t& x, const bb_params_t& y) { return model(x) < model(y) * 0.999; });
+    if (cands.size() > 6) cands.resize(6);
     // synthetic band of the (capped) shape, timed on `stream`
     void *band = nullptr, *dbuf = nullptr;
     const size_t band_bytes = (size_t)nt * (size_t)(bt + 1) * (size_t)elem;
@@ -820,23 +939,12 @@ extern "C" int bb_autotune(int64_t n, int64_t b, bb_dtype_t dtype, void* stream,
     rc = check_hip(bbk::launch_fill_synth(dtype, band, (int64_t)(band_bytes / elem), 0x5eed, st));
     if (!rc) rc = check_hip(hipEventCreate(&e0));
     if (!rc) rc = check_hip(hipEventCreate(&e1));
-    bb_params_t best = ranked.front().second;
-    float best_ms = 1e30f;
-    // one untimed run warms the memory pool and the code, then one timed run each
-    if (!rc) rc = reduce_impl(nt, bt, dtype, band, bt + 1, d, e, st, ds, ranked.front().second, false);
-    for (size_t i = 0; i < ranked.size() && !rc; ++i) {
-        const bb_params_t& c = ranked[i].second;
-        rc = check_hip(hipEventRecord(e0, st));
-        if (!rc) rc = reduce_impl(nt, bt, dtype, band, bt + 1, d, e, st, ds, c, false);
-        if (!rc) rc = check_hip(hipEventRecord(e1, st));
-        if (!rc) rc = check_hip(hipEventSynchronize(e1));
-        float ms = 0.f;
-        if (!rc) rc = check_hip(hipEventElapsedTime(&ms, e0, e1));
-        if (!rc && read_err_word(ds, false)) rc = BB_ERR_TIMEOUT;
-        if (!rc && ms < best_ms) {
-            best_ms = ms;
-            best = c;
-        }
+    std::vector<float> ms;
+    for (size_t i = 0; i < cands.size() && !rc; ++i) {
+        float t = 0.f;
+        rc = time_median([&] { return reduce_impl(nt, bt, dtype, band, bt + 1, d, e, st, ds, cands[i], false); }, st,
+                         ds, e0, e1, &t);
+        ms.push_back(t);
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -844,8 +952,102 @@ extern "C" int bb_autotune(int64_t n, int64_t b, bb_dtype_t dtype, void* stream,
     (void)hipFreeAsync(band, st);
     if (hipStreamSynchronize(st) != hipSuccess && !rc) rc = BB_ERR_HIP;
     if (rc) return rc;
+    const bb_params_t best = cands[pick_winner(ms)];
     bbp::autotune_store(n, bb, dtype, bbp::Tuned{best});
     report(best);
+    return BB_OK;
+}
+
+extern "C" int bb_autotune_batched(int64_t count, const int64_t* n, const int64_t* b, bb_dtype_t dtype, void* stream,
+                                   bb_params_t* out) {
+    if (count < 0 || count > (1 << 20)) return -1;
+    if (count > 0 && (!n || !b)) return !n ? -2 : -3;
+    if (dtype != BB_F64 && dtype != BB_F32 && dtype != BB_F16) return -4;
+    for (int64_t i = 0; i < count; ++i) {
+        if (n[i] < 0 || n[i] > (int64_t)1 << 30) return -2;
+        if (b[i] < 0) return -3;
+    }
+    DeviceState* ds = nullptr;
+    int rc = device_state(&ds);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const bb_params_t user = current_params();
+    int64_t max_n = 0, max_b = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        max_n = std::max(max_n, n[i]);
+        max_b = std::max(max_b, std::min(b[i], std::max<int64_t>(n[i] - 1, 0)));
+    }
+    auto report = [&](const bb_params_t& p) {
+        Launch L = resolve(max_n, max_b, dtype, ds->lds_per_block, p, false, 4);
+        if (out) *out = bb_params_t{L.tw, L.ntl, L.lanes, L.groups_per_cu, L.lag, L.xcd_run};
+    };
+    if (count == 0 || max_n < 2) {
+        report(user);
+        return BB_OK;
+    }
+    // synthetic bands of the batch's shapes (one buffer), outputs, pointer arrays
+    const size_t elem = elem_size(dtype);
+    std::vector<size_t> off((size_t)count);
+    size_t tot = 0, tot_d = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        off[(size_t)i] = tot;
+        tot += align_up((size_t)std::max<int64_t>(n[i], 1) * (size_t)(b[i] + 1) * elem, 256);
+        tot_d += 2 * (size_t)std::max<int64_t>(n[i], 1);
+    }
+    void *bands = nullptr, *dbuf = nullptr;
+    if (hipMallocAsync(&bands, tot, st) != hipSuccess) return BB_ERR_NOMEM;
+    if (hipMallocAsync(&dbuf, sizeof(double) * tot_d, st) != hipSuccess) {
+        (void)hipFreeAsync(bands, st);
+        return BB_ERR_NOMEM;
+    }
+    std::vector<const void*> bp((size_t)count);
+    std::vector<int64_t> ld((size_t)count);
+    std::vector<double*> dp((size_t)count), ep((size_t)count);
+    double* dd = static_cast<double*>(dbuf);
+    for (int64_t i = 0; i < count; ++i) {
+        bp[(size_t)i] = static_cast<char*>(bands) + off[(size_t)i];
+        ld[(size_t)i] = b[i] + 1;
+        dp[(size_t)i] = dd;
+        ep[(size_t)i] = dd + std::max<int64_t>(n[i], 1);
+        dd += 2 * (size_t)std::max<int64_t>(n[i], 1);
+    }
+    rc = check_hip(bbk::launch_fill_synth((int)dtype, bands, (int64_t)(tot / elem), 0xba7c, st));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!rc) rc = check_hip(hipEventCreate(&e0));
+    if (!rc) rc = check_hip(hipEventCreate(&e1));
+    size_t nplans0 = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        nplans0 = g_batch_plans.size();
+    }
+    const std::vector<bb_params_t> cands = tune_candidates(dtype, true, user);
+    std::vector<float> ms;
+    std::vector<BatchPlan*> plans;
+    for (size_t i = 0; i < cands.size() && !rc; ++i) {
+        Launch L = resolve(max_n, max_b, dtype, ds->lds_per_block, cands[i], false, 4);
+        BatchPlan* P = nullptr;
+        if (L.tw < 1 || L.tw > bbp::max_tw(dtype)) rc = BB_ERR_UNSUPPORTED;
+        if (!rc) rc = batch_plan(count, n, b, dtype, L, st, &P);
+        float t = 0.f;
+        if (!rc)
+            rc = time_median([&] { return batch_run(P, ds, bp.data(), ld.data(), dp.data(), ep.data(), L, st); }, st,
+                             ds, e0, e1, &t);
+        ms.push_back(t);
+        plans.push_back(P);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFreeAsync(dbuf, st);
+    (void)hipFreeAsync(bands, st);
+    if (hipStreamSynchronize(st) != hipSuccess && !rc) rc = BB_ERR_HIP;
+    if (rc) {
+        batch_plans_drop_after(nplans0, nullptr);
+        return rc;
+    }
+    const size_t w = pick_winner(ms);
+    batch_plans_drop_after(nplans0, plans[w]);  // the winner's plan serves the caller's next calls
+    batch_tuned_store(count, n, b, dtype, cands[w]);
+    report(cands[w]);
     return BB_OK;
 }
 

@@ -87,16 +87,18 @@ __device__ __forceinline__ double nrm2_finish(bool notbig, double asml, double a
     return scl * sqrt(sumsq);
 }
 
-// General xNRM2 over lanes 1..m of xm, each value first multiplied knt times by
-// 2^970 (the xLARFG rescaling).  Rarely taken: a rolled loop reading one lane
-// per iteration keeps it small without a call (a call would spill registers).
-__device__ __forceinline__ double nrm2_lanes_general(double xm, int m, int knt) {
+// General xNRM2 over entries 1..m: entry t < 64 is lane t of xm, entry 64 (only
+// with a 65-entry vector) is the wave-uniform xh; each value is first multiplied
+// knt times by 2^970 (the xLARFG rescaling).  Rarely taken: a rolled loop reading
+// one lane per iteration keeps it small without a call (a call would spill
+// registers).
+__device__ __forceinline__ double nrm2_lanes_general(double xm, double xh, int m, int knt) {
     constexpr double rsafmn = 2.220446049250313e-16 / 2.2250738585072014e-308;  // 1 / safmin = 2^970
     bool notbig = true;
     double asml = 0.0, amed = 0.0, abig = 0.0;
 #pragma unroll 1
     for (int t = 1; t <= m; ++t) {
-        double xt = readlane_f64(xm, t);
+        double xt = t < kWave ? readlane_f64(xm, t) : xh;
 #pragma unroll 1
         for (int i = 0; i < knt; ++i) xt = xt * rsafmn;
         nrm2_uniform_step(fabs(xt), notbig, asml, amed, abig);
@@ -112,31 +114,37 @@ __device__ __forceinline__ double lapy2(double a, double b) {
     return w * sqrt(1.0 + q * q);
 }
 
-// x_lane: lane t (0 <= t <= m) holds x_t.  On return v[0..TWM] holds the
-// reflector (v[0] = 1, v[t] = 0 for t > m), equal on every lane of the wave,
-// generated through a per-wave LDS scratch `scr` of 2 (TWM + 1) doubles:
-// lane t writes x_t^2 and later x_t / (alpha - beta), every lane reads them back
-// (broadcast reads), so no lane-by-lane register broadcast is needed.  The
-// squares are summed left to right in the same order and operations as the
-// plain definition.  All 64 lanes of the wave must be active.
+// x_lane: lane t (0 <= t <= min(m, 63)) holds x_t; with TWM = 64 the 65th entry
+// x_64 comes in the wave-uniform x_hi (read only when m = 64).  On return
+// v[0..TWM] holds the reflector (v[0] = 1, v[t] = 0 for t > m), equal on every
+// lane of the wave, generated through a per-wave LDS scratch `scr` of
+// 2 (TWM + 1) doubles: lane t writes x_t^2 and later x_t / (alpha - beta) (lane 0
+// also the entries of x_hi), every lane reads them back (broadcast reads), so no
+// lane-by-lane register broadcast is needed.  The squares are summed left to
+// right in the same order and operations as the plain definition.  All 64 lanes
+// of the wave must be active.
 template <int TWM, typename V>
-__device__ __forceinline__ void house_lds(double x_lane, int m, double* scr, V (&v)[TWM + 1], double& tau,
-                                          double& beta) {
-    static_assert(TWM < kWave, "one lane per entry");
+__device__ __forceinline__ void house_lds(double x_lane, double x_hi, int m, double* scr, V (&v)[TWM + 1],
+                                          double& tau, double& beta) {
+    static_assert(TWM <= kWave, "one lane per entry, and one more held wave-uniform");
+    constexpr bool kHi = TWM == kWave;
     constexpr double tsml = 0x1p-511, tbig = 0x1p486;
     const int lane = threadIdx.x & (kWave - 1);
     const double xm = mask_above(x_lane, m);  // lanes above m hold +0
+    const double xh = kHi && m >= kWave ? x_hi : 0.0;
     double alpha = readlane_f64(xm, 0);
-    const double ax = fabs(xm);
+    const double ax = fabs(xm), axh = fabs(xh);
     // every nonzero |x_t| (1 <= t <= m) in [tsml, tbig]: plain sum of squares
     const bool lane_ok = lane == 0 || ax == 0.0 || (ax >= tsml && ax <= tbig);
-    const bool mid = __ballot(!lane_ok) == 0;
+    const bool hi_ok = axh == 0.0 || (axh >= tsml && axh <= tbig);
+    const bool mid = __ballot(!lane_ok) == 0 && hi_ok;
     if (lane <= TWM) scr[lane] = ax * ax;
+    if (kHi && lane == 0) scr[kWave] = axh * axh;
     __builtin_amdgcn_wave_barrier();
     double amed = 0.0;
 #pragma unroll
     for (int t = 1; t <= TWM; ++t) amed = amed + scr[t];
-    double xn = mid ? sqrt(amed) : nrm2_lanes_general(xm, m, 0);
+    double xn = mid ? sqrt(amed) : nrm2_lanes_general(xm, xh, m, 0);
     v[0] = V(1);
     if (xn == 0.0) {
 #pragma unroll
@@ -156,16 +164,20 @@ __device__ __forceinline__ void house_lds(double x_lane, int m, double* scr, V (
             bt = bt * rsafmn;
             alpha = alpha * rsafmn;
         } while (fabs(bt) < safmin && knt < 20);
-        xn = nrm2_lanes_general(xm, m, knt);
+        xn = nrm2_lanes_general(xm, xh, m, knt);
         h = lapy2(alpha, xn);
         bt = alpha >= 0.0 ? -h : h;
     }
     const double scal = 1.0 / (alpha - bt);
-    double xs = xm;  // this lane's x_t, rescaled like the reference (exact powers of two)
+    double xs = xm, xhs = xh;  // this lane's x_t (and x_64), rescaled like the reference (exact powers of two)
 #pragma unroll 1
-    for (int i = 0; i < knt; ++i) xs = xs * rsafmn;
+    for (int i = 0; i < knt; ++i) {
+        xs = xs * rsafmn;
+        xhs = xhs * rsafmn;
+    }
     V* sv = reinterpret_cast<V*>(scr + TWM + 1);
     if (lane <= TWM) sv[lane] = static_cast<V>(xs * scal);  // x_t == 0 for t > m
+    if (kHi && lane == 0) sv[kWave] = static_cast<V>(xhs * scal);
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int t = 1; t <= TWM; ++t) v[t] = sv[t];

@@ -355,13 +355,15 @@ __device__ __forceinline__ double right_task(T* __restrict__ A, int64_t S, int S
     const int rows = p + m - k;  // rows k+1 .. p+m
     const Rsrc base = make_rsrc(wave_uniform(A + k + (int64_t)p * S));  // A(k, p)
     const double xl = static_cast<double>(buf_ld<T>(base, min(lane, m) * S32, 0));
+    // the 65th entry A(k, p+64) of a 64-wide tile (wave-uniform; used only when m = 64)
+    const double xh = TWM >= kWave ? static_cast<double>(buf_ld<T>(base, min(kWave, m) * S32, 0)) : 0.0;
     int ri = ltid;
     C av[TWM + 1];
     const bool early = !split || ri < p - 2 - k;  // row k+1+ri <= p-2
     if (early) load_row<T, C, TWM>(av, base, S32, 1 + min(ri, rows - 1), m);
     C vs[TWM + 1];
     double taud, betad;
-    house_lds<TWM>(xl, m, scr, vs, taud, betad);
+    house_lds<TWM>(xl, xh, m, scr, vs, taud, betad);
     if (!wait_b()) return betad;
     if (rowk_now && ltid <= m) buf_st<T>(base, ltid * S32, 0, static_cast<T>(ltid == 0 ? betad : 0.0));
     if (!early) load_row<T, C, TWM>(av, base, S32, 1 + min(ri, rows - 1), m);
@@ -407,6 +409,7 @@ __device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32,
     const gptr<T> colp = to_global(A + p + (int64_t)p * S);  // A(p, p), column p
     C* blk = stage + wv * (kWave * LDC);
     const double xl = static_cast<double>(corner[min(lane, m) * LDC]);
+    const double xh = TWM >= kWave ? static_cast<double>(corner[min(kWave, m) * LDC]) : 0.0;
     C av[TWM + 1];
     // Column ci of this thread: global rows (clamped to the window), or the corner.
     // The wave's block of columns c0 .. c0+63 is addressed from its first column
@@ -426,7 +429,7 @@ __device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32,
     if (c_first < cols && early) load_cols(cbase, c_first, ci);
     C vs[TWM + 1];
     double taud, betad;
-    house_lds<TWM>(xl, m, scr, vs, taud, betad);
+    house_lds<TWM>(xl, xh, m, scr, vs, taud, betad);
     if (!wait_b()) return;
     if (c_first < cols && !early) load_cols(cbase, c_first, ci);
     const C tau = static_cast<C>(taud);
@@ -541,6 +544,8 @@ struct GroupArgs {
 // pipeline was aborted.
 template <typename T, int TWM, int NTL>
 __device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
+    // threads 0..m of a lane write a row / column segment of m + 1 <= TWM + 1 entries
+    static_assert(NTL > TWM, "a 64-wide tile needs at least two waves per lane");
     using C = typename Compute<T>::type;
     constexpr int LDC = TWM + 1;
     const int tid = threadIdx.x;
@@ -973,19 +978,26 @@ static hipError_t launch_stage_t(const StageArgs& a, int lanes, int grid, hipStr
 template <typename T, int TWM>
 static hipError_t launch_stage_nt(const StageArgs& a, int ntl, int lanes, int grid, hipStream_t st) {
     switch (ntl) {
-        case 64: return launch_stage_t<T, TWM, 64>(a, lanes, grid, st);
+        case 64:
+            if constexpr (TWM < kWave) return launch_stage_t<T, TWM, 64>(a, lanes, grid, st);
+            return hipErrorInvalidValue;
         case 128: return launch_stage_t<T, TWM, 128>(a, lanes, grid, st);
         case 256: return launch_stage_t<T, TWM, 256>(a, lanes, grid, st);
         default: return hipErrorInvalidValue;
     }
 }
 
+// Tile widths 33..64 exist for the reduced-precision storage types only (their
+// 65-entry rows fit the registers; FP64 would not).
 template <typename T>
 static hipError_t launch_stage_tw(const StageArgs& a, int twm, int ntl, int lanes, int grid, hipStream_t st) {
     switch (twm) {
         case 8: return launch_stage_nt<T, 8>(a, ntl, lanes, grid, st);
         case 16: return launch_stage_nt<T, 16>(a, ntl, lanes, grid, st);
         case 32: return launch_stage_nt<T, 32>(a, ntl, lanes, grid, st);
+        case 64:
+            if constexpr (!std::is_same<T, double>::value) return launch_stage_nt<T, 64>(a, ntl, lanes, grid, st);
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
@@ -1001,7 +1013,9 @@ static hipError_t launch_batched_t(const BatchArgs& a, int lanes, int grid, hipS
 template <typename T, int TWM>
 static hipError_t launch_batched_nt(const BatchArgs& a, int ntl, int lanes, int grid, hipStream_t st) {
     switch (ntl) {
-        case 64: return launch_batched_t<T, TWM, 64>(a, lanes, grid, st);
+        case 64:
+            if constexpr (TWM < kWave) return launch_batched_t<T, TWM, 64>(a, lanes, grid, st);
+            return hipErrorInvalidValue;
         case 128: return launch_batched_t<T, TWM, 128>(a, lanes, grid, st);
         case 256: return launch_batched_t<T, TWM, 256>(a, lanes, grid, st);
         default: return hipErrorInvalidValue;
@@ -1014,6 +1028,9 @@ static hipError_t launch_batched_tw(const BatchArgs& a, int twm, int ntl, int la
         case 8: return launch_batched_nt<T, 8>(a, ntl, lanes, grid, st);
         case 16: return launch_batched_nt<T, 16>(a, ntl, lanes, grid, st);
         case 32: return launch_batched_nt<T, 32>(a, ntl, lanes, grid, st);
+        case 64:
+            if constexpr (!std::is_same<T, double>::value) return launch_batched_nt<T, 64>(a, ntl, lanes, grid, st);
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
@@ -1063,7 +1080,9 @@ hipError_t launch_extract_batched(int dtype, const BatchMatrix* mats, int count,
     }
 }
 
-int stage_max_threads(int twm) { return twm >= 32 ? max_threads<32>() : twm >= 16 ? max_threads<16>() : max_threads<8>(); }
+int stage_max_threads(int twm) {
+    return twm >= 64 ? max_threads<64>() : twm >= 32 ? max_threads<32>() : twm >= 16 ? max_threads<16>() : max_threads<8>();
+}
 
 size_t stage_lds_bytes(int dtype, int twm, int ntl, int lanes) {
     // same layout as LaneLds<C, TWM, NTL>

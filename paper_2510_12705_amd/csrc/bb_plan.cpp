@@ -54,7 +54,9 @@ int default_lanes(int threads_per_lane, int dtype) {
     return 1;
 }
 
-int kernel_twm(int tw) { return tw <= 8 ? 8 : tw <= 16 ? 16 : 32; }
+int kernel_twm(int tw) { return tw <= 8 ? 8 : tw <= 16 ? 16 : tw <= 32 ? 32 : 64; }
+
+int max_tw(int dtype) { return dtype == 0 ? 32 : 64; }
 
 // Window of one step (rows k..p+m of columns p..p+m, and rows p..p+m of columns
 // p..L) holds (m+1)(L-k+1) elements; it is read and written once.

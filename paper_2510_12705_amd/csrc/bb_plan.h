@@ -11,7 +11,9 @@
 
 namespace bbp {
 
-constexpr int kMaxTW = 32;
+constexpr int kMaxTW = 64;  // widest compiled tile (FP32 / FP16 storage)
+// widest tile of a storage type: 32 for FP64, 64 for FP32 / FP16
+int max_tw(int dtype);
 
 struct Stage {
     int b;    // bandwidth entering the stage

@@ -12,14 +12,18 @@
 // replaced by -pivmin, the usual safeguard of bisection for symmetric
 // tridiagonals.  A group of kSect lanes finds sigma_j of the descending order --
 // the eigenvalue of T with index t = 2n-1-j in ascending order -- by
-// multisection of [0, Gershgorin bound]: each lane evaluates the count at one of
-// kSect equally spaced interior points, and the group keeps the subinterval with
-// count(lo) <= t < count(hi), so every step divides the interval by kSect + 1
-// (about 26 steps instead of 62 bisections), until it is below 4 eps of its
-// upper end or 2^-60 of the bound.  The count is a serial chain of divisions;
-// more lanes per value also give each SIMD more waves to hide its latency.
-// Every lane walks the same entries in the same order, so the loads of d and e
-// are wave-uniform.
+// multisection of [0, Gershgorin bound]: each lane evaluates the count at kPts
+// of the kSect * kPts equally spaced interior points (two independent division
+// chains in flight per lane), and the group keeps the subinterval with
+// count(lo) <= t < count(hi), so every step divides the interval by
+// kSect * kPts + 1 (about 19 steps instead of 62 bisections), until it is below
+// 4 eps of its upper end or 2^-60 of the bound.  The quotient b^2 / q is formed
+// from the hardware reciprocal refined by one Newton step (relative error a few
+// ulps instead of a correctly rounded division): a Sturm count only needs each
+// pivot to small relative accuracy, the premise of its backward error bound.
+// The Gershgorin bound and the pivot floor are reduced once per wave (each lane
+// strides over the entries), not recomputed by every lane.  Every lane walks the
+// same entries in the same order, so the loads of d and e are wave-uniform.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -30,37 +34,65 @@ namespace bbk {
 
 constexpr int kWaveSize = 64;
 
-__device__ __forceinline__ int tgk_count_below(const double* __restrict__ d, const double* __restrict__ e, int n,
-                                               double x, double pivmin) {
-    double q = -x;
-    if (fabs(q) < pivmin) q = -pivmin;
-    int cnt = q < 0.0;
-    for (int i = 0; i < n; ++i) {
-        q = -x - (d[i] * d[i]) / q;
-        if (fabs(q) < pivmin) q = -pivmin;
-        cnt += q < 0.0;
-        if (i + 1 < n) {
-            q = -x - (e[i] * e[i]) / q;
-            if (fabs(q) < pivmin) q = -pivmin;
-            cnt += q < 0.0;
-        }
-    }
-    return cnt;
+// b2 / q for |q| >= pivmin (a normal number): reciprocal plus one Newton step
+__device__ __forceinline__ double quot(double b2, double q) {
+    double r = __builtin_amdgcn_rcp(q);
+    r = fma(r, fma(-q, r, 1.0), r);
+    return b2 * r;
 }
 
-constexpr int kSect = 4;  // lanes per singular value (divides the wave size; 4 measured fastest)
+__device__ __forceinline__ double pivot(double x, double b2, double q, double pivmin) {
+    q = -x - quot(b2, q);
+    return fabs(q) < pivmin ? -pivmin : q;
+}
+
+constexpr int kSect = 4;  // lanes per singular value (divides the wave size)
+constexpr int kPts = 2;   // count evaluations per lane and step (independent chains)
+
+// Sturm counts of T - x_p I for the kPts points x[p], walked together.
+__device__ __forceinline__ void tgk_counts_below(const double* __restrict__ d, const double* __restrict__ e, int n,
+                                                 const double (&x)[kPts], double pivmin, int (&cnt)[kPts]) {
+    double q[kPts];
+#pragma unroll
+    for (int p = 0; p < kPts; ++p) {
+        q[p] = -x[p];
+        if (fabs(q[p]) < pivmin) q[p] = -pivmin;
+        cnt[p] = q[p] < 0.0;
+    }
+    for (int i = 0; i < n; ++i) {
+        const double d2 = d[i] * d[i];
+#pragma unroll
+        for (int p = 0; p < kPts; ++p) {
+            q[p] = pivot(x[p], d2, q[p], pivmin);
+            cnt[p] += q[p] < 0.0;
+        }
+        if (i + 1 < n) {
+            const double e2 = e[i] * e[i];
+#pragma unroll
+            for (int p = 0; p < kPts; ++p) {
+                q[p] = pivot(x[p], e2, q[p], pivmin);
+                cnt[p] += q[p] < 0.0;
+            }
+        }
+    }
+}
 
 __global__ void bb_tgk_bisect(const double* __restrict__ d, const double* __restrict__ e, int n,
                               double* __restrict__ sigma) {
-    // Gershgorin bound of T (|lambda| <= |b_{i-1}| + |b_i|) and the pivot floor
-    double bound = 0.0, bmax2 = 0.0, prev = 0.0;
-    for (int i = 0; i < 2 * n - 1; ++i) {
-        const double b = fabs((i & 1) ? e[i >> 1] : d[i >> 1]);
-        bound = fmax(bound, prev + b);
+    // Gershgorin bound of T (|lambda| <= |b_{i-1}| + |b_i|, b_{-1} = b_{2n-1} = 0) and
+    // the pivot floor, reduced over the wave: lane l takes i = l, l + 64, ...
+    const int lane = threadIdx.x & (kWaveSize - 1);
+    auto offd = [&](int i) { return (i < 0 || i > 2 * n - 2) ? 0.0 : fabs((i & 1) ? e[i >> 1] : d[i >> 1]); };
+    double bound = 0.0, bmax2 = 0.0;
+    for (int i = lane; i < 2 * n; i += kWaveSize) {
+        const double b = offd(i);
+        bound = fmax(bound, offd(i - 1) + b);
         bmax2 = fmax(bmax2, b * b);
-        prev = b;
     }
-    bound = fmax(bound, prev);
+    for (int o = kWaveSize / 2; o >= 1; o >>= 1) {
+        bound = fmax(bound, __shfl_xor(bound, o, kWaveSize));
+        bmax2 = fmax(bmax2, __shfl_xor(bmax2, o, kWaveSize));
+    }
     const double pivmin = 2.2250738585072014e-308 * fmax(1.0, bmax2);
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int j = (int)(gid / kSect), k = (int)(gid % kSect);
@@ -70,11 +102,20 @@ __global__ void bb_tgk_bisect(const double* __restrict__ d, const double* __rest
     double lo = 0.0;
     double hi = bound * (1.0 + 4.0 * eps) + pivmin;
     const double floor_width = bound * 0x1p-60;
+    constexpr int kDiv = kSect * kPts + 1;
     // lo and hi are equal on the group's lanes, so the loop is uniform per group
     for (int it = 0; it < 128 && hi - lo > fmax(4.0 * eps * hi, floor_width); ++it) {
-        const double x = lo + (hi - lo) * (double)(k + 1) / (double)(kSect + 1);
-        const bool above = tgk_count_below(d, e, n, x, pivmin) > t;
-        double nh = above ? x : hi, nl = above ? lo : x;
+        double x[kPts];
+        int cnt[kPts];
+#pragma unroll
+        for (int p = 0; p < kPts; ++p) x[p] = lo + (hi - lo) * (double)(k * kPts + p + 1) / (double)kDiv;
+        tgk_counts_below(d, e, n, x, pivmin, cnt);
+        double nh = hi, nl = lo;
+#pragma unroll
+        for (int p = 0; p < kPts; ++p) {
+            if (cnt[p] > t) nh = fmin(nh, x[p]);
+            else nl = fmax(nl, x[p]);
+        }
 #pragma unroll
         for (int o = 1; o < kSect; o <<= 1) {
             nh = fmin(nh, __shfl_xor(nh, o, kWaveSize));

@@ -51,9 +51,15 @@ def bandwidth_sweep(n=16384, bandwidths=(16, 32, 64, 128, 256)):
 
 
 def ragged_batch(count=512, seed=5):
+    """The ragged batch as configured: the batched FP32 call with parameters from
+    bb_autotune_batched, captured once into a hipGraph and replayed, against a
+    loop of plain FP32 bb_reduce calls on one stream (and the untuned eager
+    batched call for reference).  Replays are timed with events on the capture
+    stream (median of 5 after a warm-up replay)."""
     import torch
 
     from . import bb, inputs
+    bb.release()
     bb.reset_params()
     mats = inputs.ragged_batch(count=count, seed=seed)
     bands = [torch.from_numpy(np.ascontiguousarray(bd)).cuda().to(torch.float32) for (_, _, bd) in mats]
@@ -61,7 +67,33 @@ def ragged_batch(count=512, seed=5):
     bs = [m[1] for m in mats]
     ds = [torch.empty(max(x, 1), dtype=torch.float64, device="cuda") for x in ns]
     es = [torch.empty(max(x, 1), dtype=torch.float64, device="cuda") for x in ns]
-    t_batch = _best_ms(torch, lambda: bb.bb_reduce_batched(bands, ns, bs, ds=ds, es=es))
+    t_default = _best_ms(torch, lambda: bb.bb_reduce_batched(bands, ns, bs, ds=ds, es=es))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        p = bb.autotune_batched(ns, bs, bb.F32, stream=s)
+        bb.bb_reduce_batched(bands, ns, bs, ds=ds, es=es, stream=s)   # plan for this stream, tuned
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    t_tuned_eager = _best_ms(torch, lambda: bb.bb_reduce_batched(bands, ns, bs, ds=ds, es=es, stream=s))
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        bb.bb_reduce_batched(bands, ns, bs, ds=ds, es=es, stream=s)
+    g.replay()
+    torch.cuda.synchronize()
+    assert bb.stream_status(s) == 0
+    times = []
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(s):   # replay() launches on the current stream
+            e0.record()
+            g.replay()
+            e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    t_graph = float(np.median(times))
+    bb.reset_params()
 
     def loop():
         for t, x, y, d, e in zip(bands, ns, bs, ds, es):
@@ -69,8 +101,11 @@ def ragged_batch(count=512, seed=5):
 
     t_loop = _best_ms(torch, loop)
     alg = sum(bb.model_bytes(x, y, 4, TW_REF[4]) for x, y in zip(ns, bs))
-    print("%d ragged FP32 bands: batched %.1f ms, loop of single calls %.1f ms (%.2fx); %.1f%% roofline" % (
-        count, t_batch, t_loop, t_loop / t_batch, 100 * alg / (t_batch / 1e3) / PEAK_BYTES_PER_S), flush=True)
+    print("%d ragged FP32 bands: graph replay of the autotuned batched call %.1f ms (%r); eager tuned %.1f ms, "
+          "eager defaults %.1f ms; loop of single calls %.1f ms (%.2fx the graph replay); %.1f%% roofline" % (
+              count, t_graph, p, t_tuned_eager, t_default, t_loop, t_loop / t_graph,
+              100 * alg / (t_graph / 1e3) / PEAK_BYTES_PER_S), flush=True)
+    bb.release()
 
 
 def bidiag_sigma(n=32768, b=128):

@@ -76,7 +76,7 @@ def test_params_roundtrip_and_rejection():
     p = bb.get_params()
     assert (p.tw, p.threads_per_window, p.sweeps_per_group, p.groups_per_cu, p.lag, p.xcd_run) == (8, 128, 4, 2, 0, 5)
     with pytest.raises(bb.BBError):
-        bb.set_params(tw=40)
+        bb.set_params(tw=65)   # widest compiled tile is 64 (FP32 / FP16 storage)
     with pytest.raises(bb.BBError):
         bb.set_params(threads_per_window=96)
     with pytest.raises(bb.BBError):
