@@ -6,8 +6,8 @@
  * super-diagonals, compute an upper bidiagonal B = U^T A V (U, V orthogonal,
  * U e1 = V e1 = e1) by bulge chasing with two-sided Householder reflectors,
  * reducing the bandwidth in stages of TW (the "inner tilewidth").  Singular
- * values are preserved: sigma(B) = sigma(A).  Only the bidiagonal (d, e) is
- * returned; the orthogonal factors are not formed.
+ * values are preserved: sigma(B) = sigma(A).  bb_reduce returns the bidiagonal
+ * (d, e); bb_reduce_vectors also forms U and V.
  *
  * Conventions shared by every entry point
  *   - Band layout (input): LAPACK column-major upper band of the storage type,
@@ -132,6 +132,31 @@ int bb_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void *band, int64_t 
  */
 int bb_reduce_noalloc(int64_t n, int64_t b, bb_dtype_t dtype, const void *band, int64_t ldband,
                       double *d, double *e, void *stream);
+
+/*
+ * bb_reduce that also forms the orthogonal factors: U^T A V = bidiag(d, e),
+ * U e1 = V e1 = e1.  The paper returns only the bidiagonal and names the
+ * singular vectors as the extension (Sec. I, closing paragraph; Sec. VII): the
+ * reflectors of the bulge chase are kept (its Algorithm 2 writes each one back
+ * in place of the entries it annihilates) and applied afterwards.  Here every
+ * reflector (tau, v in FP64, for every storage type) is logged during the
+ * reduction and U = H_1 H_2 ... (left reflectors in the order applied), V
+ * likewise from the right reflectors, are accumulated from the identity on the
+ * device.  d, e are bitwise those of bb_reduce; for BB_F64, U and V equal a plain
+ * sequential FP64 accumulation in the reduction's order bitwise (up to the sign
+ * of zero).
+ *   U, V     device pointers to n x n column-major FP64 matrices with leading
+ *            dimensions ldu, ldv >= max(n, 1) (outputs); either may be NULL (not
+ *            formed).
+ * Other arguments as bb_reduce.  Argument numbers: n=1, b=2, dtype=3, band=4,
+ * ldband=5, d=6, e=7, U=8, ldu=9, V=10, ldv=11.  Working memory (stream-ordered,
+ * freed by the call) is bb_workspace_bytes plus the reflector log: per stage
+ * (b_s, TW_s), 2 (n - c_s - 1)(1 + (n - 2 - c_s) / b_s)(TW + 1) doubles, about
+ * 100 MB at n = 2048, b = 64 and 37 GB at n = 32768, b = 128.
+ */
+int bb_reduce_vectors(int64_t n, int64_t b, bb_dtype_t dtype, const void *band, int64_t ldband,
+                      double *d, double *e, double *U, int64_t ldu, double *V, int64_t ldv,
+                      void *stream);
 
 /*
  * Reduce `count` independent bands of uneven n_i, b_i in one persistent launch

@@ -47,6 +47,8 @@ def _load():
     i64, vp, dp, ip = ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
     lib.bb_reduce.argtypes = [i64, i64, ctypes.c_int, vp, i64, vp, vp, vp]
     lib.bb_reduce.restype = ctypes.c_int
+    lib.bb_reduce_vectors.argtypes = [i64, i64, ctypes.c_int, vp, i64, vp, vp, vp, i64, vp, i64, vp]
+    lib.bb_reduce_vectors.restype = ctypes.c_int
     lib.bb_reduce_noalloc.argtypes = [i64, i64, ctypes.c_int, vp, i64, vp, vp, vp]
     lib.bb_reduce_noalloc.restype = ctypes.c_int
     lib.bb_reduce_batched.argtypes = [i64, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.c_int,
@@ -89,7 +91,7 @@ def _load():
 
 lib = _load()
 
-EXPORTS = ("bb_reduce", "bb_reduce_noalloc", "bb_reduce_batched", "bb_set_params", "bb_get_params", "bb_autotune", "bb_autotune_batched", "bb_resolved_params",
+EXPORTS = ("bb_reduce", "bb_reduce_vectors", "bb_reduce_noalloc", "bb_reduce_batched", "bb_set_params", "bb_get_params", "bb_autotune", "bb_autotune_batched", "bb_resolved_params",
            "bb_workspace_bytes", "bb_model_bytes", "bb_plan", "bb_min_lag", "bb_stream_status",
            "bb_release", "bb_error_string", "bb_timing_enable", "bb_timing_read", "bb_bidiag_sigma")
 
@@ -131,6 +133,35 @@ def bb_reduce(band, n: int, b: int, d=None, e=None, stream=None, ldband: int | N
                        ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(e.data_ptr()), _stream_handle(stream))
     _check(rc, "bb_reduce")
     return d[:n], e[:max(n - 1, 0)]
+
+
+def bb_reduce_vectors(band, n: int, b: int, want_u: bool = True, want_v: bool = True, stream=None,
+                      ldband: int | None = None):
+    """Reduce a device band and form the orthogonal factors: returns (d, e, U, V)
+    with U^T A V = bidiag(d, e); U and V are float64 device tensors holding the
+    n x n matrices (column-major storage, viewed as the matrix; None if not
+    asked for)."""
+    import torch
+    if not band.is_cuda:
+        raise ValueError("band must be a device tensor")
+    if not band.is_contiguous():
+        raise ValueError("band must be contiguous (n, ldband)")
+    ld = ldband if ldband is not None else (band.shape[1] if band.dim() == 2 else b + 1)
+    dev = band.device
+    d = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    e = torch.empty(max(n - 1, 1), dtype=torch.float64, device=dev)
+    m = max(n, 1)
+    Ut = torch.empty((m, m), dtype=torch.float64, device=dev) if want_u else None   # rows of Ut = columns of U
+    Vt = torch.empty((m, m), dtype=torch.float64, device=dev) if want_v else None
+    rc = lib.bb_reduce_vectors(n, b, _torch_dtype_code(band), ctypes.c_void_p(band.data_ptr()), ld,
+                               ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(e.data_ptr()),
+                               ctypes.c_void_p(Ut.data_ptr() if Ut is not None else None), m,
+                               ctypes.c_void_p(Vt.data_ptr() if Vt is not None else None), m,
+                               _stream_handle(stream))
+    _check(rc, "bb_reduce_vectors")
+    U = Ut[:n, :n].t() if Ut is not None else None
+    V = Vt[:n, :n].t() if Vt is not None else None
+    return d[:n], e[:max(n - 1, 0)], U, V
 
 
 def bb_reduce_noalloc(band, n: int, b: int, d, e, stream=None, ldband: int | None = None):

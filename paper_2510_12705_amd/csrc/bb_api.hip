@@ -514,12 +514,38 @@ static int prepare_call(int64_t n, int64_t b, int dtype, DeviceState* ds, const 
     return BB_OK;
 }
 
+// Reflector log of a call that forms the singular vectors: per stage, right-task
+// slots [step j][sweep r] then left-task slots, wlog doubles each (tau, v_1..v_TW).
+struct VecLog {
+    double* base = nullptr;
+    int wlog = 0;
+    std::vector<int64_t> off;     // per stage: offset of its slots (doubles)
+    std::vector<int> nsteps;      // per stage: steps of its longest sweep (sweep 0)
+    int64_t doubles = 0;          // total size
+};
+
+static VecLog veclog_layout(int64_t n, int64_t bb, int tw) {
+    VecLog v;
+    if (bb <= 1) return v;
+    v.wlog = bbp::stage_first(bb, tw).tw + 1;
+    for (bbp::Stage sg = bbp::stage_first(bb, tw);; sg = bbp::stage_next(sg, tw)) {
+        const int64_t nsw = std::max<int64_t>(n - sg.c - 1, 0);
+        const int nst = nsw > 0 ? (int)(1 + (n - 2 - sg.c) / sg.b) : 0;
+        v.off.push_back(v.doubles);
+        v.nsteps.push_back(nst);
+        v.doubles += 2 * (int64_t)nst * nsw * v.wlog;
+        if (sg.c <= 1) break;
+    }
+    return v;
+}
+
 // Enqueue the whole reduction on `st` with working memory at `base` (c.ws.total
 // bytes, 256-byte aligned): zero the counters, pack, one stage kernel per
 // bandwidth-reduction stage, extract.  Allocates nothing on the device; with
 // `timing_allowed` and timing enabled it creates one event pair per stage launch.
+// With `vl` the stage kernels also log every reflector there.
 static int enqueue_call(const Call& c, const void* band, int64_t ldband, double* d, double* e, hipStream_t st,
-                        DeviceState* ds, char* base, bool timing_allowed) {
+                        DeviceState* ds, char* base, bool timing_allowed, const VecLog* vl = nullptr) {
     const Launch& L = c.L;
     const Workspace& ws = c.ws;
     const int64_t n = c.n;
@@ -549,6 +575,8 @@ static int enqueue_call(const Call& c, const void* band, int64_t ldband, double*
         a.spin_limit = spin_limit();
         a.nxcd = ds->nxcd > 1 && L.xcd_run > 0 ? ds->nxcd : 0;
         a.xcd_run = std::max(L.xcd_run, 1);
+        a.vlog = vl && vl->base ? vl->base + vl->off[(size_t)s] : nullptr;
+        a.wlog = vl ? vl->wlog : 0;
         if (a.nsweeps == 0) continue;
         if (dtype == BB_F16) rc = check_hip(bbk::launch_f16_rescale(W, n * ws.ldw, f16_amax + s, f16_exps, s, st));
         if (rc) break;
@@ -627,6 +655,50 @@ int bb_reduce_noalloc(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, 
     if (rc) return rc;
     if (c.ws.total > kScratchBytes) return BB_ERR_SCRATCH;
     return enqueue_call(c, band, ldband, d, e, (hipStream_t)stream, ds, ds->scratch_dev, false);
+}
+
+// bb_reduce that also forms U and V: the stage kernels log their reflectors in
+// stream-ordered working memory, then one back-transformation launch per stage
+// applies them to X = I (U from the left reflectors, V from the right ones).
+int bb_reduce_vectors(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, int64_t ldband, double* d, double* e,
+                      double* U, int64_t ldu, double* V, int64_t ldv, void* stream) {
+    if (n < 0 || n > ((int64_t)1 << 30)) return -1;
+    if (b < 0) return -2;
+    if (dtype != BB_F64 && dtype != BB_F32 && dtype != BB_F16) return -3;
+    if (n > 0 && !band) return -4;
+    if (ldband < b + 1) return -5;
+    if (n > 0 && !d) return -6;
+    if (n > 1 && !e) return -7;
+    if (U && ldu < std::max<int64_t>(n, 1)) return -9;
+    if (V && ldv < std::max<int64_t>(n, 1)) return -11;
+    if (n == 0) return BB_OK;
+    DeviceState* ds = nullptr;
+    int rc = device_state(&ds);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    Call c;
+    rc = prepare_call(n, b, dtype, ds, current_params(), true, &c);
+    if (rc) return rc;
+    VecLog vl = veclog_layout(n, c.bb, c.L.tw);
+    const size_t total = c.ws.total + align_up(sizeof(double) * (size_t)vl.doubles, 256);
+    void* base = nullptr;
+    if (hipMallocAsync(&base, total, st) != hipSuccess) return BB_ERR_NOMEM;
+    vl.base = vl.doubles > 0 ? reinterpret_cast<double*>(static_cast<char*>(base) + c.ws.total) : nullptr;
+    rc = enqueue_call(c, band, ldband, d, e, st, ds, static_cast<char*>(base), true, &vl);
+    if (!rc && U) rc = check_hip(bbk::launch_identity(U, n, ldu, st));
+    if (!rc && V) rc = check_hip(bbk::launch_identity(V, n, ldv, st));
+    if (!rc && vl.base) {
+        size_t s = 0;
+        for (bbp::Stage sg = bbp::stage_first(c.bb, c.L.tw); !rc; sg = bbp::stage_next(sg, c.L.tw), ++s) {
+            const int nsw = (int)std::max<int64_t>(n - sg.c - 1, 0);
+            rc = check_hip(bbk::launch_backtransform(V, ldv, U, ldu, (int)n, sg.b, sg.tw, sg.c, nsw, vl.nsteps[s],
+                                                     vl.base + vl.off[s], vl.wlog, st));
+            if (sg.c <= 1) break;
+        }
+    }
+    hipError_t fe = hipFreeAsync(base, st);
+    if (!rc && fe != hipSuccess) rc = BB_ERR_HIP;
+    return rc;
 }
 
 int bb_reduce_batched(int64_t count, const int64_t* n, const int64_t* b, bb_dtype_t dtype, const void* const* band,

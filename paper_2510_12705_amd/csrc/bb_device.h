@@ -123,9 +123,12 @@ __device__ __forceinline__ double lapy2(double a, double b) {
 // lane-by-lane register broadcast is needed.  The squares are summed left to
 // right in the same order and operations as the plain definition.  All 64 lanes
 // of the wave must be active.
+// v_own receives this lane's FP64 entry v_lane (0 above m; lane 0's value is not
+// v_0 = 1 and is not meant to be used) and v_hi_own the FP64 v_64 of a 65-entry
+// vector; the reflector log of the singular-vector path stores them.
 template <int TWM, typename V>
 __device__ __forceinline__ void house_lds(double x_lane, double x_hi, int m, double* scr, V (&v)[TWM + 1],
-                                          double& tau, double& beta) {
+                                          double& tau, double& beta, double& v_own, double& v_hi_own) {
     static_assert(TWM <= kWave, "one lane per entry, and one more held wave-uniform");
     constexpr bool kHi = TWM == kWave;
     constexpr double tsml = 0x1p-511, tbig = 0x1p486;
@@ -151,6 +154,8 @@ __device__ __forceinline__ void house_lds(double x_lane, double x_hi, int m, dou
         for (int t = 1; t <= TWM; ++t) v[t] = V(0);
         tau = 0.0;
         beta = alpha;
+        v_own = 0.0;
+        v_hi_own = 0.0;
         return;
     }
     double h = lapy2(alpha, xn);
@@ -175,9 +180,11 @@ __device__ __forceinline__ void house_lds(double x_lane, double x_hi, int m, dou
         xs = xs * rsafmn;
         xhs = xhs * rsafmn;
     }
+    v_own = xs * scal;  // x_t == 0 for t > m
+    v_hi_own = xhs * scal;
     V* sv = reinterpret_cast<V*>(scr + TWM + 1);
-    if (lane <= TWM) sv[lane] = static_cast<V>(xs * scal);  // x_t == 0 for t > m
-    if (kHi && lane == 0) sv[kWave] = static_cast<V>(xhs * scal);
+    if (lane <= TWM) sv[lane] = static_cast<V>(v_own);
+    if (kHi && lane == 0) sv[kWave] = static_cast<V>(v_hi_own);
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int t = 1; t <= TWM; ++t) v[t] = sv[t];

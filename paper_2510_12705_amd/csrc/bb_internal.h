@@ -22,6 +22,10 @@ struct StageArgs {
     unsigned spin_limit;
     int nxcd;           // XCDs of the device (0: groups are claimed in one global order)
     int xcd_run;        // consecutive groups placed on one XCD (>= 1; used when nxcd > 0)
+    double* vlog;       // reflector log (null: none): [side][step j][sweep r][wlog] doubles,
+                        // side 0 = right (row) reflectors, 1 = left (column) reflectors;
+                        // a slot holds tau, v_1 .. v_{wlog-1} (zero above m)
+    int wlog;           // doubles per slot (TW of the call + 1)
 };
 
 // ---- ragged batch ----
@@ -72,6 +76,12 @@ hipError_t launch_fill_synth(int dtype, void* p, int64_t count, uint64_t seed, h
 hipError_t launch_f16_rescale(void* W, int64_t count, unsigned* amax, int* exps, int s, hipStream_t st);
 hipError_t launch_extract_f16(const void* W, int64_t n, int64_t ldw, int64_t uo, const int* exps, int nexp,
                               double* d, double* e, hipStream_t st);
+// Singular vectors: X = I (n x n, leading dimension ldx), then X <- X H for every
+// reflector of one side of one stage, from that stage's log (see StageArgs::vlog).
+// Xv (from the right reflectors) or Xu (from the left ones) may be null.
+hipError_t launch_identity(double* X, int64_t n, int64_t ldx, hipStream_t st);
+hipError_t launch_backtransform(double* Xv, int64_t ldv, double* Xu, int64_t ldu, int n, int b, int tw, int c,
+                                int nsweeps, int nsteps, const double* log, int wlog, hipStream_t st);
 // sigma of bidiag(d, e), descending, by bisection on the Golub-Kahan tridiagonal
 hipError_t launch_bidiag_sigma(const double* d, const double* e, int64_t n, double* sigma, hipStream_t st);
 // largest workgroup (ntl * lanes) the stage kernel variant for tilewidth bound twm accepts

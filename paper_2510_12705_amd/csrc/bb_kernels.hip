@@ -330,6 +330,21 @@ __device__ __forceinline__ StepGeom step_geom(int n, int b, int tw, int c, int r
     return g;
 }
 
+// Reflector log of the singular-vector path: the first wave of a task writes its
+// reflector's tau and v_1..v_TWM (FP64, zero above m) to the task's slot of
+// `wlog` entries; lane 0 also writes v_64 of a 65-entry reflector.  v_0 = 1 is
+// implicit.  `slot` is null when nothing is logged.
+template <int TWM>
+__device__ __forceinline__ void log_reflector(gptr<double> slot, int wlog, int ltid, double tau, double v_own,
+                                              double v_hi_own) {
+    if (ltid >= kWave) return;
+    if (ltid == 0) slot[0] = tau;
+    else if (ltid < wlog) slot[ltid] = v_own;
+    if constexpr (TWM >= kWave) {
+        if (ltid == 0 && kWave < wlog) slot[kWave] = v_hi_own;
+    }
+}
+
 // half-steps of sweep r (2 per step); sweep r exists iff r <= n - c - 2
 __device__ __forceinline__ int sweep_halfsteps(int n, int b, int c, int r) { return 2 * (1 + (n - 2 - r - c) / b); }
 
@@ -347,7 +362,8 @@ __device__ __forceinline__ int sweep_halfsteps(int n, int b, int c, int r) { ret
 template <typename T, int TWM, int NTL, typename WaitB>
 __device__ __forceinline__ double right_task(T* __restrict__ A, int64_t S, int S32, StepGeom g,
                                              typename Compute<T>::type* corner, double* scr, int ltid,
-                                             bool split, bool rowk_now, WaitB&& wait_b) {
+                                             bool split, bool rowk_now, gptr<double> vlog, int wlog,
+                                             WaitB&& wait_b) {
     using C = typename Compute<T>::type;
     constexpr int LDC = TWM + 1;
     const int k = uni(g.k), p = uni(g.p), m = uni(g.m);  // a wave never spans two sweeps
@@ -362,8 +378,9 @@ __device__ __forceinline__ double right_task(T* __restrict__ A, int64_t S, int S
     const bool early = !split || ri < p - 2 - k;  // row k+1+ri <= p-2
     if (early) load_row<T, C, TWM>(av, base, S32, 1 + min(ri, rows - 1), m);
     C vs[TWM + 1];
-    double taud, betad;
-    house_lds<TWM>(xl, xh, m, scr, vs, taud, betad);
+    double taud, betad, v_own, v_hi;
+    house_lds<TWM>(xl, xh, m, scr, vs, taud, betad, v_own, v_hi);
+    if (vlog) log_reflector<TWM>(vlog, wlog, ltid, taud, v_own, v_hi);
     if (!wait_b()) return betad;
     if (rowk_now && ltid <= m) buf_st<T>(base, ltid * S32, 0, static_cast<T>(ltid == 0 ? betad : 0.0));
     if (!early) load_row<T, C, TWM>(av, base, S32, 1 + min(ri, rows - 1), m);
@@ -399,7 +416,7 @@ template <typename T, int TWM, int NTL, typename WaitB>
 __device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32, StepGeom g, int n, int b,
                                           const typename Compute<T>::type* corner,
                                           typename Compute<T>::type* stage, double* scr, int ltid,
-                                          bool split, WaitB&& wait_b) {
+                                          bool split, gptr<double> vlog, int wlog, WaitB&& wait_b) {
     using C = typename Compute<T>::type;
     constexpr int LDC = TWM + 1;
     const int p = uni(g.p), m = uni(g.m);  // a wave never spans two sweeps
@@ -428,8 +445,9 @@ __device__ __forceinline__ void left_task(T* __restrict__ A, int64_t S, int S32,
     const bool early = !split || ci <= b - 3 || ci >= cols;
     if (c_first < cols && early) load_cols(cbase, c_first, ci);
     C vs[TWM + 1];
-    double taud, betad;
-    house_lds<TWM>(xl, xh, m, scr, vs, taud, betad);
+    double taud, betad, v_own, v_hi;
+    house_lds<TWM>(xl, xh, m, scr, vs, taud, betad, v_own, v_hi);
+    if (vlog) log_reflector<TWM>(vlog, wlog, ltid, taud, v_own, v_hi);
     if (!wait_b()) return;
     if (c_first < cols && !early) load_cols(cbase, c_first, ci);
     const C tau = static_cast<C>(taud);
@@ -534,6 +552,9 @@ struct GroupArgs {
     const int* stage_prev;   // progress word of the last group of the previous stage; must be
                              // DONE before phase 0 (null: no wait)
     int* last;               // this group's progress word
+    double* vlog;            // reflector log of this stage (null: not logged): right-task slots
+                             // [j][r] then left-task slots [j][r], wlog doubles each
+    int wlog;
     int* abort_flag;
     int* err_word;
     unsigned spin_limit;
@@ -563,6 +584,7 @@ __device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
     const int n = ga.n, b = ga.b, tw = ga.tw, c = ga.c, H = ga.H;
     const int r0 = ga.r0;
     const int nl = min(G, ga.nsweeps - r0);
+    const int64_t side_slots = (int64_t)(sweep_halfsteps(n, b, c, 0) / 2) * ga.nsweeps;  // steps x sweeps
     const int r = r0 + g;
     const bool has_sweep = g < nl;
     const int len = has_sweep ? sweep_halfsteps(n, b, c, r) : 0;
@@ -647,8 +669,13 @@ __device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
         StepGeom sg{0, 0, 0};
         if (active) {
             sg = step_geom(n, b, tw, c, r, h >> 1);
+            gptr<double> slot = nullptr;
+            if (ga.vlog)
+                slot = to_global(ga.vlog) +
+                       (((h & 1) * side_slots + (int64_t)(h >> 1) * ga.nsweeps + r) * (int64_t)ga.wlog);
             if ((h & 1) == 0) {
-                beta_row = right_task<T, TWM, NTL>(A, S, S32, sg, corner, scr, ltid, split, rowk_now, wait_b);
+                beta_row = right_task<T, TWM, NTL>(A, S, S32, sg, corner, scr, ltid, split, rowk_now, slot, ga.wlog,
+                                                   wait_b);
             } else {
                 // row k of this step's right task (read by every wave of the lane in
                 // the previous phase) becomes (beta, 0, ..., 0), after the full wait
@@ -659,7 +686,8 @@ __device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
                                  static_cast<T>(ltid == 0 ? beta_row : 0.0));
                     return true;
                 };
-                left_task<T, TWM, NTL>(A, S, S32, sg, n, b, corner, stage, scr, ltid, split, wait_b_rowk);
+                left_task<T, TWM, NTL>(A, S, S32, sg, n, b, corner, stage, scr, ltid, split, slot, ga.wlog,
+                                       wait_b_rowk);
             }
         }
         if (!waited) wait_b();  // keeps the barrier count equal when no task ran
@@ -754,6 +782,8 @@ __global__ __launch_bounds__(max_threads<TWM>()) void bb_stage(StageArgs a) {
         ga.prev = q > 0 ? a.progress + (q - 1) : nullptr;
         ga.stage_prev = nullptr;
         ga.last = a.progress + q;
+        ga.vlog = a.vlog;
+        ga.wlog = a.wlog;
         ga.abort_flag = a.abort_flag;
         ga.err_word = a.err_word;
         ga.spin_limit = a.spin_limit;
@@ -806,6 +836,8 @@ __global__ __launch_bounds__(max_threads<TWM>()) void bb_stage_batched(BatchArgs
             ga.stage_prev = a.progress + Sp.prog_off + Sp.ngroups - 1;
         }
         ga.last = a.progress + St.prog_off + tk.group;
+        ga.vlog = nullptr;
+        ga.wlog = 0;
         ga.abort_flag = a.abort_flag;
         ga.err_word = a.err_word;
         ga.spin_limit = a.spin_limit;

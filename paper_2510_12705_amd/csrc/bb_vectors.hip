@@ -1,0 +1,192 @@
+// bb_vectors.hip -- the orthogonal factors of the reduction, B = U^T A V.
+//
+// The paper keeps only the bidiagonal and names the singular vectors as the
+// extension (its introduction's closing paragraph and Sec. VII): the reflectors
+// that the bulge chase generates must be kept and applied afterwards.  The stage
+// kernels log every reflector (tau and v in FP64, v_0 = 1 implicit) of a call
+// that asks for the factors; here U = H_1 H_2 ... (the left reflectors in the
+// order the reduction applied them) and V likewise from the right reflectors are
+// formed by X <- X H_i starting from X = I.
+//
+// A row x of X is independent of the other rows, so one thread owns one row.
+// Within a stage the reflectors are taken step by step in decreasing order and,
+// for each step j, sweep by sweep in increasing order: the support p..p+m of
+// (r, j), p = r + c + j b, then slides by one column per sweep, so the thread
+// keeps the row's W = TWM + 1 entries of the current support, and the next few
+// columns, in a ring of registers (the loop over sweeps is unrolled over
+// the ring so that every index is a compile-time constant) and, per reflector,
+// stores the column that leaves the window and loads the one that many
+// reflectors ahead; the reflectors themselves are staged through LDS one pass
+// over the ring ahead.  Reflectors of one side whose
+// supports share a column are met in the same relative order as in the
+// reduction (same step: by sweep; different steps: they can only meet when the
+// sweep of the larger step comes first), so every entry of X undergoes the same
+// operations in the same order as under the sequential order; the dot product
+// and the update are the plain sequential ones (no fused multiply-add), so FP64
+// results equal a plain sequential accumulation bit for bit (up to the sign of
+// zero).  Entries of v above m are logged as 0, and columns beyond n - 1 are
+// held as 0 and never stored.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "bb_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace bbk {
+
+template <typename T>
+using gptr_v = __attribute__((address_space(1))) T*;
+
+constexpr int kWaveLanes = 64;
+
+__global__ void bb_identity(double* __restrict__ X, int64_t n, int64_t ldx) {
+    const int64_t total = n * n;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = idx / n, i = idx - j * n;
+        X[i + j * ldx] = i == j ? 1.0 : 0.0;
+    }
+}
+
+// blockIdx.y = 0: V from the right reflectors, 1: U from the left reflectors.
+// One wave per workgroup.  The ring holds R = W + ahead columns: the column that
+// enters at sweep r is loaded `ahead` reflectors before its first use, so its
+// latency hides behind that many dot products.  The reflectors of one pass over
+// the ring (R consecutive sweeps of one step: R * wlog contiguous log entries)
+// sit in one of two LDS buffers; while a pass runs, the next pass's entries are
+// loaded in chunks of kChunk reflectors (coalesced, each chunk issued at the
+// start of the matching chunk of this pass and written to the other buffer at
+// its end), so few registers hold them and their latency is hidden.
+template <int TWM>
+constexpr int ring_ahead() { return TWM >= 64 ? 8 : 16; }
+template <int TWM>
+constexpr int ring_size() { return TWM + 1 + ring_ahead<TWM>(); }
+constexpr int kChunk = 16;
+
+template <int TWM>
+__global__ __launch_bounds__(64) void bb_backtransform(double* __restrict__ Xv, int64_t ldv, double* __restrict__ Xu,
+                                                       int64_t ldu, int n, int b, int c, int nsweeps, int nsteps,
+                                                       const double* __restrict__ log, int wlog) {
+    constexpr int W = TWM + 1;
+    constexpr int R = ring_size<TWM>();
+    constexpr int PASS = R * W;                                 // LDS entries of one pass (wlog <= W)
+    constexpr int CE = kChunk * W;                              // entries of one chunk
+    constexpr int Q = (CE + kWaveLanes - 1) / kWaveLanes;       // chunk entries per lane
+    constexpr int NCH = (R + kChunk - 1) / kChunk;              // chunks per pass
+    extern __shared__ double vbuf[];                            // [2][R][W]
+    double* __restrict__ X = blockIdx.y == 0 ? Xv : Xu;
+    const int64_t ldx = blockIdx.y == 0 ? ldv : ldu;
+    if (!X) return;
+    const int lane = threadIdx.x;
+    const int64_t side_slots = (int64_t)nsteps * nsweeps;
+    const double* __restrict__ lg = log + (blockIdx.y == 0 ? 0 : side_slots * wlog);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool row = i < n;  // lanes past the last row compute on zeros and store nothing
+    gptr_v<double> xi = (gptr_v<double>)(X + (row ? i : 0));
+    auto ld = [&](int col) -> double { return (row && col < n) ? xi[(int64_t)col * ldx] : 0.0; };
+    // chunk k of the pass starting at sweep r0: entries of sweeps r0 + k*kChunk + u'
+    // (u' < kChunk, within the pass) as [u][t], zero beyond wlog or rcount
+    auto fetch = [&](const double* __restrict__ slots, int r0, int k, int rcount, double (&q)[Q]) {
+#pragma unroll
+        for (int z = 0; z < Q; ++z) {
+            const int e = lane + kWaveLanes * z;  // entry of the chunk: u' * W + t
+            const int up = e / W, t = e - up * W;
+            const int u = k * kChunk + up;        // reflector of the pass
+            const int r = r0 + u;
+            q[z] = (e < CE && u < R && t < wlog && r < rcount) ? slots[(int64_t)r * wlog + t] : 0.0;
+        }
+    };
+    auto stage = [&](int buf, int k, const double (&q)[Q]) {
+#pragma unroll
+        for (int z = 0; z < Q; ++z) {
+            const int e = lane + kWaveLanes * z;
+            const int u = k * kChunk + e / W;
+            if (e < CE && u < R) vbuf[buf * PASS + k * CE + e] = q[z];
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
+    for (int j = nsteps - 1; j >= 0; --j) {
+        const int rcount = min(n - 1 - c - j * b, nsweeps);  // sweeps with p = r + c + j b <= n - 2
+        if (rcount <= 0) continue;
+        const int p0 = c + j * b;
+        double x[R];  // slot s holds column p0 + s + R k during the k-th pass over the ring
+#pragma unroll
+        for (int t = 0; t < R; ++t) x[t] = ld(p0 + t);
+        const double* __restrict__ slots = lg + (int64_t)j * nsweeps * wlog;
+        double q[Q];
+        __builtin_amdgcn_wave_barrier();  // the previous step's last pass has read its buffer
+        for (int k = 0; k < NCH; ++k) {
+            fetch(slots, 0, k, rcount, q);
+            stage(0, k, q);
+        }
+        int buf = 0;
+        for (int rb = 0; rb < rcount; rb += R) {
+            const double* vb = vbuf + buf * PASS;
+#pragma clang loop unroll(full)
+            for (int u = 0; u < R; ++u) {
+                if (u % kChunk == 0) fetch(slots, rb + R, u / kChunk, rcount, q);  // next pass, this chunk
+                const int r = rb + u;
+                if (r < rcount) {
+                    const double* sl = vb + u * W;
+                    const double tau = sl[0];
+                    if (tau != 0.0) {
+                        // support p .. p + W - 1 (p = p0 + r) sits in slots u, u+1, ... (mod R)
+                        double w = 0.0;
+                        w = w + x[u] * 1.0;
+#pragma clang loop unroll(full)
+                        for (int t = 1; t < W; ++t) w = w + x[(u + t) % R] * sl[t];
+                        const double tw = tau * w;
+                        x[u] = x[u] - tw * 1.0;
+#pragma clang loop unroll(full)
+                        for (int t = 1; t < W; ++t) x[(u + t) % R] = x[(u + t) % R] - tw * sl[t];
+                    }
+                    // column p leaves the window for good in this step; column p + R enters its slot
+                    const int p = p0 + r;
+                    if (row) xi[(int64_t)p * ldx] = x[u];
+                    x[u] = ld(p + R);
+                }
+                if (u % kChunk == kChunk - 1 || u == R - 1) stage(buf ^ 1, u / kChunk, q);
+            }
+            buf ^= 1;
+        }
+        // slot s holds column p0 + s + R * (number of sweeps r < rcount with r = s mod R)
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+            const int passes = rcount > s ? (rcount - s + R - 1) / R : 0;
+            const int col = p0 + s + R * passes;
+            if (row && col < n) xi[(int64_t)col * ldx] = x[s];
+        }
+    }
+}
+
+hipError_t launch_identity(double* X, int64_t n, int64_t ldx, hipStream_t st) {
+    if (!X || n <= 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>((n * n + 255) / 256, 8192);
+    hipLaunchKernelGGL(bb_identity, dim3(grid), dim3(256), 0, st, X, n, ldx);
+    return hipGetLastError();
+}
+
+template <int TWM>
+static void launch_bt(dim3 grid, hipStream_t st, double* Xv, int64_t ldv, double* Xu, int64_t ldu, int n, int b, int c,
+                      int nsweeps, int nsteps, const double* log, int wlog) {
+    const size_t lds = sizeof(double) * 2 * (size_t)ring_size<TWM>() * (TWM + 1);
+    hipLaunchKernelGGL(bb_backtransform<TWM>, grid, dim3(kWaveLanes), lds, st, Xv, ldv, Xu, ldu, n, b, c, nsweeps,
+                       nsteps, log, wlog);
+}
+
+hipError_t launch_backtransform(double* Xv, int64_t ldv, double* Xu, int64_t ldu, int n, int b, int tw, int c,
+                                int nsweeps, int nsteps, const double* log, int wlog, hipStream_t st) {
+    if ((!Xv && !Xu) || n <= 1 || nsweeps <= 0 || nsteps <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((n + kWaveLanes - 1) / kWaveLanes), 2);
+    if (tw <= 8) launch_bt<8>(grid, st, Xv, ldv, Xu, ldu, n, b, c, nsweeps, nsteps, log, wlog);
+    else if (tw <= 16) launch_bt<16>(grid, st, Xv, ldv, Xu, ldu, n, b, c, nsweeps, nsteps, log, wlog);
+    else if (tw <= 32) launch_bt<32>(grid, st, Xv, ldv, Xu, ldu, n, b, c, nsweeps, nsteps, log, wlog);
+    else if (tw <= 64) launch_bt<64>(grid, st, Xv, ldv, Xu, ldu, n, b, c, nsweeps, nsteps, log, wlog);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace bbk

@@ -55,6 +55,12 @@ def test_argument_validation_without_device():
     assert L.bb_reduce_noalloc(8, 4, 0, dummy, 5, None, dummy, None) == -6
     assert L.bb_reduce_noalloc(8, 4, 0, dummy, 5, dummy, None, None) == -7
     assert L.bb_reduce_noalloc(0, 4, 0, None, 5, None, None, None) == 0
+    # the singular-vector entry point: the same checks plus the factors' leading dimensions
+    assert L.bb_reduce_vectors(-1, 4, 0, dummy, 5, dummy, dummy, None, 0, None, 0, None) == -1
+    assert L.bb_reduce_vectors(8, 4, 3, dummy, 5, dummy, dummy, None, 0, None, 0, None) == -3
+    assert L.bb_reduce_vectors(8, 4, 0, dummy, 5, dummy, dummy, dummy, 7, None, 0, None) == -9
+    assert L.bb_reduce_vectors(8, 4, 0, dummy, 5, dummy, dummy, None, 0, dummy, 7, None) == -11
+    assert L.bb_reduce_vectors(0, 4, 0, None, 5, None, None, None, 0, None, 0, None) == 0
     I64 = ctypes.c_int64 * 1
     VP = ctypes.c_void_p * 1
     assert L.bb_reduce_batched(-1, None, None, 0, None, None, None, None, None) == -1
