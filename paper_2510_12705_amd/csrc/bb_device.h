@@ -92,13 +92,14 @@ __device__ __forceinline__ double nrm2_finish(bool notbig, double asml, double a
 // knt times by 2^970 (the xLARFG rescaling).  Rarely taken: a rolled loop reading
 // one lane per iteration keeps it small without a call (a call would spill
 // registers).
+template <bool kHi>
 __device__ __forceinline__ double nrm2_lanes_general(double xm, double xh, int m, int knt) {
     constexpr double rsafmn = 2.220446049250313e-16 / 2.2250738585072014e-308;  // 1 / safmin = 2^970
     bool notbig = true;
     double asml = 0.0, amed = 0.0, abig = 0.0;
 #pragma unroll 1
     for (int t = 1; t <= m; ++t) {
-        double xt = t < kWave ? readlane_f64(xm, t) : xh;
+        double xt = (kHi && t >= kWave) ? xh : readlane_f64(xm, t);
 #pragma unroll 1
         for (int i = 0; i < knt; ++i) xt = xt * rsafmn;
         nrm2_uniform_step(fabs(xt), notbig, asml, amed, abig);
@@ -147,7 +148,7 @@ __device__ __forceinline__ void house_lds(double x_lane, double x_hi, int m, dou
     double amed = 0.0;
 #pragma unroll
     for (int t = 1; t <= TWM; ++t) amed = amed + scr[t];
-    double xn = mid ? sqrt(amed) : nrm2_lanes_general(xm, xh, m, 0);
+    double xn = mid ? sqrt(amed) : nrm2_lanes_general<kHi>(xm, xh, m, 0);
     v[0] = V(1);
     if (xn == 0.0) {
 #pragma unroll
@@ -169,7 +170,7 @@ __device__ __forceinline__ void house_lds(double x_lane, double x_hi, int m, dou
             bt = bt * rsafmn;
             alpha = alpha * rsafmn;
         } while (fabs(bt) < safmin && knt < 20);
-        xn = nrm2_lanes_general(xm, xh, m, knt);
+        xn = nrm2_lanes_general<kHi>(xm, xh, m, knt);
         h = lapy2(alpha, xn);
         bt = alpha >= 0.0 ? -h : h;
     }

@@ -563,7 +563,7 @@ struct GroupArgs {
 // Executed by the whole workgroup (G lanes of NTL threads).  In phase P lane g
 // runs half-step P - H*g of sweep r0+g; see bb_stage below.  Returns false if the
 // pipeline was aborted.
-template <typename T, int TWM, int NTL>
+template <typename T, int TWM, int NTL, bool LOG>
 __device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
     // threads 0..m of a lane write a row / column segment of m + 1 <= TWM + 1 entries
     static_assert(NTL > TWM, "a 64-wide tile needs at least two waves per lane");
@@ -670,7 +670,7 @@ __device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
         if (active) {
             sg = step_geom(n, b, tw, c, r, h >> 1);
             gptr<double> slot = nullptr;
-            if (ga.vlog)
+            if constexpr (LOG)
                 slot = to_global(ga.vlog) +
                        (((h & 1) * side_slots + (int64_t)(h >> 1) * ga.nsweeps + r) * (int64_t)ga.wlog);
             if ((h & 1) == 0) {
@@ -732,7 +732,7 @@ __device__ bool run_group(const GroupArgs& ga, unsigned char* lds, int* s_ok) {
 // progress[q] is group q's word: half-steps completed by its last sweep, then
 // kDone once it and every earlier group finished.
 // ---------------------------------------------------------------------------
-template <typename T, int TWM, int NTL>
+template <typename T, int TWM, int NTL, bool LOG>
 __global__ __launch_bounds__(max_threads<TWM>()) void bb_stage(StageArgs a) {
     using C = typename Compute<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -787,7 +787,7 @@ __global__ __launch_bounds__(max_threads<TWM>()) void bb_stage(StageArgs a) {
         ga.abort_flag = a.abort_flag;
         ga.err_word = a.err_word;
         ga.spin_limit = a.spin_limit;
-        if (!run_group<T, TWM, NTL>(ga, lds, &s_ok)) return;
+        if (!run_group<T, TWM, NTL, LOG>(ga, lds, &s_ok)) return;
     }
 }
 
@@ -877,7 +877,7 @@ __global__ __launch_bounds__(max_threads<TWM>()) void bb_stage_batched(BatchArgs
                 __syncthreads();
             }
         }
-        if (!run_group<T, TWM, NTL>(ga, lds, &s_ok)) return;
+        if (!run_group<T, TWM, NTL, false>(ga, lds, &s_ok)) return;
     }
 }
 
@@ -1003,7 +1003,10 @@ template <typename T, int TWM, int NTL>
 static hipError_t launch_stage_t(const StageArgs& a, int lanes, int grid, hipStream_t st) {
     using C = typename Compute<T>::type;
     const size_t smem = (size_t)lanes * LaneLds<C, TWM, NTL>::bytes;
-    hipLaunchKernelGGL((bb_stage<T, TWM, NTL>), dim3(grid), dim3(NTL * lanes), smem, st, a);
+    if (a.vlog)
+        hipLaunchKernelGGL((bb_stage<T, TWM, NTL, true>), dim3(grid), dim3(NTL * lanes), smem, st, a);
+    else
+        hipLaunchKernelGGL((bb_stage<T, TWM, NTL, false>), dim3(grid), dim3(NTL * lanes), smem, st, a);
     return hipGetLastError();
 }
 

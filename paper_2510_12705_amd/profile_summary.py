@@ -4,6 +4,8 @@ under ``profiles/``.
   python -m paper_2510_12705_amd.profile_summary trace <kernel_stats.csv> <kernel_trace.csv> <out.md> "<command>"
   python -m paper_2510_12705_amd.profile_summary traffic <fetch_counter_collection.csv> <write_counter_collection.csv> \
       <out.json> <workload> <dtype> "<fetch command>" "<write command>" <copy MiB>
+  python -m paper_2510_12705_amd.profile_summary counters <sq_counter_collection.csv> <tcc_counter_collection.csv> \
+      <out.md> "<sq command>" "<tcc command>"
 
 ``traffic`` calibrates FETCH_SIZE / WRITE_SIZE (KiB per dispatch) against the
 device copy of known size that ``bench.py --copy-calib-mib`` runs first (the
@@ -73,10 +75,48 @@ def traffic(fetch_csv, write_csv, out_json, workload, dtype, fetch_cmd, write_cm
         json.dump(out, f, indent=1)
 
 
+def counters(sq_csv, tcc_csv, out_md, sq_cmd, tcc_cmd, simds=1024):
+    """Per stage-kernel dispatch: occupancy, L2 hit rate, LDS bank conflicts, memory
+    instruction counts.  The stage kernel is persistent (every workgroup lives until
+    the stage ends), so the waves resident per SIMD are SQ_WAVES / simds."""
+    per = {}
+    for path in (sq_csv, tcc_csv):
+        for r in _rows(path):
+            if "bb_stage" not in r["Kernel_Name"]:
+                continue
+            d = per.setdefault(int(r["Dispatch_Id"]), {"kernel": r["Kernel_Name"], "wg": r["Workgroup_Size"],
+                                                         "grid": r["Grid_Size"], "vgpr": r["VGPR_Count"]})
+            d[r["Counter_Name"]] = float(r["Counter_Value"])
+            if path == sq_csv:
+                d["ms"] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+    lines = ["# rocprofv3 counters: %s" % out_md.rsplit("/", 1)[-1].replace(".md", ""), "",
+             "Commands (from the repository root, on one MI355X; one counter pass each):", "",
+             "    %s" % sq_cmd, "", "    %s" % tcc_cmd, "",
+             "Per stage-kernel dispatch (one per bandwidth-reduction stage).  The kernel is persistent,",
+             "so waves resident per SIMD = SQ_WAVES / %d SIMDs for the whole dispatch;" % simds,
+             "L2 hit rate = TCC_HIT / (TCC_HIT + TCC_MISS); LDS conflict cycles per LDS instruction =",
+             "SQ_LDS_BANK_CONFLICT / SQ_INSTS_LDS.", "",
+             "| dispatch | kernel | ms | waves | waves/SIMD resident | L2 hit rate | LDS conflict cycles / LDS instr |"
+             " VMEM rd instr | VMEM wr instr | LDS instr |",
+             "|---:|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for k in sorted(per):
+        d = per[k]
+        occ = d.get("SQ_WAVES", 0.0) / simds
+        hit = d.get("TCC_HIT_sum", 0.0) / max(d.get("TCC_HIT_sum", 0.0) + d.get("TCC_MISS_sum", 0.0), 1.0)
+        lds = d.get("SQ_LDS_BANK_CONFLICT", 0.0) / max(d.get("SQ_INSTS_LDS", 1.0), 1.0)
+        lines.append("| %d | `%s` | %.1f | %d | %.2f | %.3f | %.4f | %.3e | %.3e | %.3e |" % (
+            k, d["kernel"][:44], d.get("ms", 0.0), int(d.get("SQ_WAVES", 0)), occ, hit, lds,
+            d.get("SQ_INSTS_VMEM_RD", 0.0), d.get("SQ_INSTS_VMEM_WR", 0.0), d.get("SQ_INSTS_LDS", 0.0)))
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace(*sys.argv[2:6])
     elif sys.argv[1] == "traffic":
         traffic(*sys.argv[2:10])
+    elif sys.argv[1] == "counters":
+        counters(*sys.argv[2:7])
     else:
         raise SystemExit(__doc__)
