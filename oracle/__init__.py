@@ -14,6 +14,10 @@ Contents
                              applies every reflector to all rows and columns (no index
                              ranges at all), for pinning the band code's ranges.
   * ``nrm2``              -- the C oracle's norm on its own, for its pins.
+  * ``sym_reduce``        -- the symmetric variant: a symmetric band reduced to
+                             tridiagonal by the same chase with one reflector per
+                             step applied from both sides (C, ``bb_oracle.c``).
+  * ``sym_eigenvalues``   -- eigenvalues of a symmetric tridiagonal, LAPACK dsterf.
   * ``singular_values``   -- sigma of a bidiagonal (d, e) as the non-negative
                              eigenvalues of its Golub-Kahan (TGK) tridiagonal, via
                              LAPACK dsterf; the paper uses LAPACK BDSDC for this step
@@ -60,6 +64,8 @@ def _load():
         lib.bbo_reduce_pipelined.restype = ctypes.c_int
         lib.bbo_nrm2.argtypes = [dp, i64]
         lib.bbo_nrm2.restype = ctypes.c_double
+        lib.bbo_sym_reduce.argtypes = [i64, i64, i64, dp, i64, dp, dp, dp]
+        lib.bbo_sym_reduce.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -92,6 +98,36 @@ def reduce(band: np.ndarray, n: int, b: int, tw: int, want_uv: bool = False, rev
     if want_uv:
         return d, e, U, V
     return d, e
+
+
+def sym_reduce(band: np.ndarray, n: int, b: int, tw: int, want_q: bool = False):
+    """Sequential FP64 reduction of a symmetric band (lower layout: an (n, ldband)
+    C-ordered array with A(i, j) = band[j, i - j] for 0 <= i - j <= b) to
+    tridiagonal (d, e); with ``want_q`` also Q with Q^T A Q = tridiag(d, e)."""
+    lib = _load()
+    band = np.ascontiguousarray(band, dtype=np.float64)
+    ldband = band.shape[1] if band.ndim == 2 else b + 1
+    d = np.zeros(max(n, 1))
+    e = np.zeros(max(n - 1, 1))
+    Q = np.zeros((n, n), order="F") if want_q else None
+    rc = lib.bbo_sym_reduce(n, b, tw, _dp(band), ldband, _dp(d), _dp(e), _dp(Q))
+    if rc != 0:
+        raise ValueError("bbo_sym_reduce failed with code %d" % rc)
+    d, e = d[:n], e[:max(n - 1, 0)]
+    return (d, e, Q) if want_q else (d, e)
+
+
+def sym_eigenvalues(d, e):
+    """Eigenvalues (ascending) of the symmetric tridiagonal with diagonal d and
+    off-diagonal e, by LAPACK dsterf."""
+    from scipy.linalg import lapack
+    d = np.array(d, dtype=np.float64)
+    if len(d) == 0:
+        return d
+    w, info = lapack.dsterf(d.copy(), np.array(e, dtype=np.float64).copy())
+    if info != 0:
+        raise RuntimeError("dsterf failed: %d" % info)
+    return np.sort(w)
 
 
 def nrm2(x) -> float:

@@ -346,3 +346,135 @@ int bbo_reduce_pipelined(int64_t n, int64_t b, int64_t TW, const double *band, i
     free(len); free(prog); free(ready); free(A.w);
     return rc;
 }
+
+/*
+ * Symmetric variant: band -> tridiagonal for the symmetric eigenvalue problem
+ * (the paper names this sister reduction as the one that bulge chasing also
+ * serves; it reduces the non-symmetric band to bidiagonal form).  The same
+ * successive band reduction and the same step geometry, with one reflector per
+ * step applied from both sides, A <- H A H.
+ *
+ *   A is n x n symmetric with b sub-diagonals, held as its lower triangle:
+ *   LAPACK lower band layout A(i, j) = band[(i - j) + j * ldband], 0 <= i - j <= b.
+ *   Stage (b, tw, c = b - tw), sweep r, step j: k, p, m as in the bidiagonal
+ *   case (step 0: k = r, p = r + c; step j: k = r + c + (j-1) b, p = k + b;
+ *   m = min(tw, n-1-p), for step 0 min(r+b, n-1) - p).  The step:
+ *     1. reflector from the column segment A[p..p+m, k]; A[p, k] = beta and
+ *        A[p+1..p+m, k] = 0 exactly;
+ *     2. left application H A on rows p..p+m of columns k+1 .. p+m, where the
+ *        (m+1) x (m+1) diagonal block is taken whole (its upper triangle is the
+ *        mirror of the stored lower one);
+ *     3. right application (H A) H on columns p..p+m of the block's rows and of
+ *        rows p+m+1 .. min(p+m+b, n-1);
+ *     4. the lower triangle of the block is stored back (its upper triangle,
+ *        equal up to rounding, is dropped).
+ *   Every dot product is summed left to right; no fused multiply-add.
+ *   Output: d = diagonal, e = sub-diagonal of the tridiagonal T = Q^T A Q
+ *   (Q e1 = e1; with Q != NULL the n x n column-major Q is accumulated by
+ *   Q <- Q H in the order the reflectors are applied).
+ */
+typedef struct {
+    int64_t n, ldw;   /* element (i, q), q <= i <= q + ldw - 1, at w[(i - q) + q * ldw] */
+    double *w;
+} bbo_sband;
+
+static inline double *sat(const bbo_sband *S, int64_t i, int64_t q) { return &S->w[(i - q) + q * S->ldw]; }
+
+static void sym_step(bbo_sband *S, int64_t b, int64_t k, int64_t p, int64_t m, double *Q) {
+    const int64_t n = S->n;
+    double x[BBO_MAXTW + 1], v[BBO_MAXTW + 1], tau, beta;
+    for (int64_t t = 0; t <= m; ++t) x[t] = *sat(S, p + t, k);
+    house(x, m, v, &tau, &beta);
+    *sat(S, p, k) = beta;
+    for (int64_t t = 1; t <= m; ++t) *sat(S, p + t, k) = 0.0;
+    if (tau == 0.0) return;
+    const int64_t w1 = m + 1;
+    double *B = (double *)malloc(sizeof(double) * (size_t)(w1 * w1));  /* B[s + t*w1] = A(p+s, p+t) */
+    for (int64_t t = 0; t < w1; ++t)
+        for (int64_t s = 0; s < w1; ++s) B[s + t * w1] = s >= t ? *sat(S, p + s, p + t) : *sat(S, p + t, p + s);
+    /* left: columns k+1 .. p-1 (rows p..p+m, all below the diagonal) */
+    for (int64_t q = k + 1; q < p; ++q) {
+        double w = 0.0;
+        for (int64_t t = 0; t <= m; ++t) w = w + v[t] * *sat(S, p + t, q);
+        double tw = tau * w;
+        for (int64_t t = 0; t <= m; ++t) *sat(S, p + t, q) = *sat(S, p + t, q) - tw * v[t];
+    }
+    /* left: the block's columns */
+    for (int64_t q = 0; q < w1; ++q) {
+        double w = 0.0;
+        for (int64_t t = 0; t < w1; ++t) w = w + v[t] * B[t + q * w1];
+        double tw = tau * w;
+        for (int64_t t = 0; t < w1; ++t) B[t + q * w1] = B[t + q * w1] - tw * v[t];
+    }
+    /* right: the block's rows */
+    for (int64_t s = 0; s < w1; ++s) {
+        double w = 0.0;
+        for (int64_t t = 0; t < w1; ++t) w = w + B[s + t * w1] * v[t];
+        double tw = tau * w;
+        for (int64_t t = 0; t < w1; ++t) B[s + t * w1] = B[s + t * w1] - tw * v[t];
+    }
+    /* right: rows p+m+1 .. L */
+    int64_t L = p + m + b;
+    if (L > n - 1) L = n - 1;
+    for (int64_t i = p + m + 1; i <= L; ++i) {
+        double w = 0.0;
+        for (int64_t t = 0; t <= m; ++t) w = w + *sat(S, i, p + t) * v[t];
+        double tw = tau * w;
+        for (int64_t t = 0; t <= m; ++t) *sat(S, i, p + t) = *sat(S, i, p + t) - tw * v[t];
+    }
+    for (int64_t t = 0; t < w1; ++t)
+        for (int64_t s = t; s < w1; ++s) *sat(S, p + s, p + t) = B[s + t * w1];
+    free(B);
+    if (Q) {  /* Q <- Q H on columns p..p+m (all rows) */
+        for (int64_t i = 0; i < n; ++i) {
+            double w = 0.0;
+            for (int64_t t = 0; t <= m; ++t) w = w + Q[i + (p + t) * n] * v[t];
+            double tw = tau * w;
+            for (int64_t t = 0; t <= m; ++t) Q[i + (p + t) * n] = Q[i + (p + t) * n] - tw * v[t];
+        }
+    }
+}
+
+/*
+ * Symmetric band (lower layout, b sub-diagonals, ldband >= b+1) -> tridiagonal
+ * (d: n diagonal entries, e: n-1 sub-diagonal entries), inner tilewidth TW.
+ * Q (may be NULL): n x n column-major with Q^T A Q = tridiag(d, e).
+ * Returns 0, -i for an invalid argument i, or 1 on allocation failure.
+ */
+int bbo_sym_reduce(int64_t n, int64_t b, int64_t TW, const double *band, int64_t ldband, double *d, double *e,
+                   double *Q) {
+    if (n < 0) return -1;
+    if (b < 0) return -2;
+    if (TW < 1 || TW > BBO_MAXTW) return -3;
+    if (!band && n > 0) return -4;
+    if (ldband < b + 1) return -5;
+    int64_t bb = b;
+    if (n > 0 && bb > n - 1) bb = n - 1;
+    int64_t tw0 = bb > 1 ? (TW < bb - 1 ? TW : bb - 1) : 0;
+    bbo_sband S;
+    S.n = n;
+    S.ldw = bb + tw0 + 2;  /* rows q .. q + b + tw of column q (fill), plus the sub-diagonal when b = 0 */
+    S.w = (double *)calloc((size_t)(S.ldw * (n > 0 ? n : 1)), sizeof(double));
+    if (!S.w) return 1;
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = j; i <= j + bb && i < n; ++i) *sat(&S, i, j) = band[(i - j) + j * ldband];
+    if (Q) { memset(Q, 0, sizeof(double) * n * n); for (int64_t i = 0; i < n; ++i) Q[i + i * n] = 1.0; }
+    int64_t bs = bb;
+    while (bs > 1) {
+        int64_t tw = TW < bs - 1 ? TW : bs - 1, c = bs - tw;
+        for (int64_t r = 0; r + c + 1 <= n - 1; ++r) {
+            for (int64_t j = 0;; ++j) {
+                int64_t k, p, m = step_geom(n, bs, tw, c, r, j, &k, &p);
+                if (m < 1) break;
+                sym_step(&S, bs, k, p, m, Q);
+            }
+        }
+        bs = c;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        d[i] = *sat(&S, i, i);
+        if (i + 1 < n) e[i] = *sat(&S, i + 1, i);
+    }
+    free(S.w);
+    return 0;
+}
