@@ -159,6 +159,31 @@ int bb_reduce_vectors(int64_t n, int64_t b, bb_dtype_t dtype, const void *band, 
                       void *stream);
 
 /*
+ * Symmetric band -> tridiagonal (the reduction for the symmetric eigenvalue
+ * problem, which the paper names as the sister use of bulge chasing; its own
+ * method is the non-symmetric band -> bidiagonal one).  The same successive
+ * band reduction and step geometry (Sec. III, Algorithm 1), with one Householder
+ * reflector per step applied from both sides (A <- H A H).  T = Q^T A Q with Q
+ * orthogonal, Q e1 = e1; eigenvalues are preserved.
+ *   band     device pointer, LAPACK LOWER band of `dtype`: A(i, j) =
+ *            band[(i - j) + j * ldband] for 0 <= i - j <= b, ldband >= b + 1
+ *            (the symmetric A's lower triangle; rows past n - 1 are ignored).
+ *   d, e     device pointers to n and max(n - 1, 0) doubles: the diagonal and
+ *            sub-diagonal of T.
+ *   dtype    BB_F64 or BB_F32 storage (reflectors in FP64); BB_F16 returns
+ *            BB_ERR_UNSUPPORTED.  Tilewidths 1..32 (bb_set_params' tw; default 32);
+ *            bb_set_params' groups_per_cu and lag apply, the other fields do not.
+ * Argument numbers as bb_reduce.  Working memory is stream-ordered and freed by
+ * the call.  FP64 results are bitwise independent of the launch shape.
+ */
+int bb_sym_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void *band, int64_t ldband,
+                  double *d, double *e, void *stream);
+
+/* Smallest safe step lag of the symmetric chase for a stage leaving bandwidth c
+ * (c >= 1): 2, or 3 when c = 1. */
+int bb_sym_min_lag(int64_t c);
+
+/*
  * Reduce `count` independent bands of uneven n_i, b_i in one persistent launch
  * that draws (matrix, stage, sweep) tasks from a device work queue.  The paper
  * has no batched form: this entry point is this library's addition; each

@@ -49,6 +49,10 @@ def _load():
     lib.bb_reduce.restype = ctypes.c_int
     lib.bb_reduce_vectors.argtypes = [i64, i64, ctypes.c_int, vp, i64, vp, vp, vp, i64, vp, i64, vp]
     lib.bb_reduce_vectors.restype = ctypes.c_int
+    lib.bb_sym_reduce.argtypes = [i64, i64, ctypes.c_int, vp, i64, vp, vp, vp]
+    lib.bb_sym_reduce.restype = ctypes.c_int
+    lib.bb_sym_min_lag.argtypes = [i64]
+    lib.bb_sym_min_lag.restype = ctypes.c_int
     lib.bb_reduce_noalloc.argtypes = [i64, i64, ctypes.c_int, vp, i64, vp, vp, vp]
     lib.bb_reduce_noalloc.restype = ctypes.c_int
     lib.bb_reduce_batched.argtypes = [i64, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.c_int,
@@ -91,7 +95,7 @@ def _load():
 
 lib = _load()
 
-EXPORTS = ("bb_reduce", "bb_reduce_vectors", "bb_reduce_noalloc", "bb_reduce_batched", "bb_set_params", "bb_get_params", "bb_autotune", "bb_autotune_batched", "bb_resolved_params",
+EXPORTS = ("bb_reduce", "bb_reduce_vectors", "bb_sym_reduce", "bb_sym_min_lag", "bb_reduce_noalloc", "bb_reduce_batched", "bb_set_params", "bb_get_params", "bb_autotune", "bb_autotune_batched", "bb_resolved_params",
            "bb_workspace_bytes", "bb_model_bytes", "bb_plan", "bb_min_lag", "bb_stream_status",
            "bb_release", "bb_error_string", "bb_timing_enable", "bb_timing_read", "bb_bidiag_sigma")
 
@@ -162,6 +166,30 @@ def bb_reduce_vectors(band, n: int, b: int, want_u: bool = True, want_v: bool = 
     U = Ut[:n, :n].t() if Ut is not None else None
     V = Vt[:n, :n].t() if Vt is not None else None
     return d[:n], e[:max(n - 1, 0)], U, V
+
+
+def bb_sym_reduce(band, n: int, b: int, d=None, e=None, stream=None, ldband: int | None = None):
+    """Reduce a symmetric band (device tensor (n, ldband), float64/32, the LAPACK
+    LOWER band: A(i, j) = band[j, i - j]) to tridiagonal.  Returns (d, e) float64
+    device tensors: diagonal and sub-diagonal."""
+    import torch
+    if not band.is_cuda:
+        raise ValueError("band must be a device tensor")
+    if not band.is_contiguous():
+        raise ValueError("band must be contiguous (n, ldband)")
+    ld = ldband if ldband is not None else (band.shape[1] if band.dim() == 2 else b + 1)
+    if d is None:
+        d = torch.empty(max(n, 1), dtype=torch.float64, device=band.device)
+    if e is None:
+        e = torch.empty(max(n - 1, 1), dtype=torch.float64, device=band.device)
+    rc = lib.bb_sym_reduce(n, b, _torch_dtype_code(band), ctypes.c_void_p(band.data_ptr()), ld,
+                           ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(e.data_ptr()), _stream_handle(stream))
+    _check(rc, "bb_sym_reduce")
+    return d[:n], e[:max(n - 1, 0)]
+
+
+def sym_min_lag(c: int) -> int:
+    return int(lib.bb_sym_min_lag(c))
 
 
 def bb_reduce_noalloc(band, n: int, b: int, d, e, stream=None, ldband: int | None = None):

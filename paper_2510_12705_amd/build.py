@@ -20,7 +20,7 @@ BUILD = os.path.join(PKG, "_build")
 LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libbb.so")
 
-SOURCES = ["bb_api.hip", "bb_kernels.hip", "bb_sigma.hip", "bb_vectors.hip", "bb_plan.cpp"]
+SOURCES = ["bb_api.hip", "bb_kernels.hip", "bb_sigma.hip", "bb_vectors.hip", "bb_sym.hip", "bb_plan.cpp"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

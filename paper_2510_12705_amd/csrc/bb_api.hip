@@ -701,6 +701,73 @@ int bb_reduce_vectors(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, 
     return rc;
 }
 
+int bb_sym_min_lag(int64_t c) { return c < 1 ? -1 : (c == 1 ? 3 : 2); }
+
+// Symmetric band -> tridiagonal: pack the lower band into a working band with
+// room for the bulge fill, one persistent stage kernel per bandwidth-reduction
+// stage, extract the diagonal and sub-diagonal.
+int bb_sym_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, int64_t ldband, double* d, double* e,
+                  void* stream) {
+    if (n < 0 || n > ((int64_t)1 << 30)) return -1;
+    if (b < 0) return -2;
+    if (dtype != BB_F64 && dtype != BB_F32 && dtype != BB_F16) return -3;
+    if (n > 0 && !band) return -4;
+    if (ldband < b + 1) return -5;
+    if (n > 0 && !d) return -6;
+    if (n > 1 && !e) return -7;
+    if (n == 0) return BB_OK;
+    if (dtype == BB_F16) return BB_ERR_UNSUPPORTED;
+    DeviceState* ds = nullptr;
+    int rc = device_state(&ds);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const bb_params_t prm = current_params();
+    const int64_t bb = std::min<int64_t>(b, n - 1);
+    const int tw = prm.tw ? prm.tw : bbp::default_tw(dtype);
+    if (tw < 1 || tw > 32) return BB_ERR_UNSUPPORTED;
+    const int tw0 = bb > 1 ? bbp::stage_first(bb, tw).tw : 0;
+    const int64_t ldw = (int64_t)align_up((size_t)(bb + tw0 + 2), 2);
+    const int nstages = bbp::stage_count(bb, tw);
+    const size_t band_bytes = align_up((size_t)n * (size_t)ldw * elem_size(dtype), 256);
+    const int64_t per_stage = n + 2;  // progress words, claim, abort
+    const size_t total = band_bytes + align_up(sizeof(int) * (size_t)(per_stage * std::max(nstages, 1)), 256);
+    void* base = nullptr;
+    if (hipMallocAsync(&base, total, st) != hipSuccess) return BB_ERR_NOMEM;
+    char* W = static_cast<char*>(base);
+    int* counters = reinterpret_cast<int*>(W + band_bytes);
+    rc = check_hip(bbk::launch_fill(counters, per_stage * std::max(nstages, 1), 0, st));
+    if (!rc) rc = check_hip(bbk::launch_sym_pack(dtype, band, ldband, n, bb, W, ldw, st));
+    const int gpc = prm.groups_per_cu ? prm.groups_per_cu : 2;
+    if (bb > 1) {
+        int s = 0;
+        for (bbp::Stage sg = bbp::stage_first(bb, tw); !rc; sg = bbp::stage_next(sg, tw), ++s) {
+            bbk::SymStageArgs a;
+            a.W = W;
+            a.ldw = ldw;
+            a.n = (int)n;
+            a.b = sg.b;
+            a.tw = sg.tw;
+            a.c = sg.c;
+            a.H = std::max(bb_sym_min_lag(sg.c), prm.lag);
+            a.nsweeps = (int)std::max<int64_t>(n - sg.c - 1, 0);
+            a.progress = counters + per_stage * s;
+            a.claim = a.progress + n;
+            a.abort_flag = a.claim + 1;
+            a.err_word = ds->err_dev;
+            a.spin_limit = spin_limit();
+            if (a.nsweeps > 0) {
+                const int grid = (int)std::min<int64_t>(a.nsweeps, (int64_t)ds->cus * gpc);
+                rc = check_hip(bbk::launch_sym_stage(dtype, a, bbp::kernel_twm(sg.tw), grid, st));
+            }
+            if (sg.c <= 1) break;
+        }
+    }
+    if (!rc) rc = check_hip(bbk::launch_sym_extract(dtype, W, n, ldw, d, e, st));
+    hipError_t fe = hipFreeAsync(base, st);
+    if (!rc && fe != hipSuccess) rc = BB_ERR_HIP;
+    return rc;
+}
+
 int bb_reduce_batched(int64_t count, const int64_t* n, const int64_t* b, bb_dtype_t dtype, const void* const* band,
                       const int64_t* ldband, double* const* d, double* const* e, void* stream) {
     if (count < 0 || count > (1 << 20)) return -1;

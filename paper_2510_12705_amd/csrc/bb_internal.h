@@ -28,6 +28,23 @@ struct StageArgs {
     int wlog;           // doubles per slot (TW of the call + 1)
 };
 
+// Arguments of one stage of the symmetric band -> tridiagonal reduction (bb_sym.hip).
+struct SymStageArgs {
+    void* W;            // working band, lower layout: A(i, q) = W[(i - q) + q * ldw]
+    int64_t ldw;
+    int n, b, tw, c, H; // order, bandwidth entering the stage, tilewidth, bandwidth left, step lag
+    int nsweeps;        // n - c - 1
+    int* progress;      // [nsweeps] steps completed per sweep (zeroed before launch)
+    int* claim;         // [1] next sweep to hand out (zeroed before launch)
+    int* abort_flag;    // [1] watchdog abort word (zeroed before launch)
+    int* err_word;
+    unsigned spin_limit;
+};
+hipError_t launch_sym_stage(int dtype, const SymStageArgs& a, int twm, int grid, hipStream_t st);
+hipError_t launch_sym_pack(int dtype, const void* band, int64_t ldband, int64_t n, int64_t b, void* W, int64_t ldw,
+                           hipStream_t st);
+hipError_t launch_sym_extract(int dtype, const void* W, int64_t n, int64_t ldw, double* d, double* e, hipStream_t st);
+
 // ---- ragged batch ----
 struct BatchStage {
     int b, tw, c, H;   // stage geometry and half-step lag

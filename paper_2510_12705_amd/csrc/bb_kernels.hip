@@ -35,22 +35,9 @@
 
 #include "bb_device.h"
 #include "bb_internal.h"
+#include "bb_window.h"
 
 namespace bbk {
-
-template <typename T>
-struct Compute {
-    using type = float;
-};
-template <>
-struct Compute<double> {
-    using type = double;
-};
-
-template <typename T>
-__device__ __forceinline__ typename Compute<T>::type to_c(T x) {
-    return static_cast<typename Compute<T>::type>(x);
-}
 
 // ---------------------------------------------------------------------------
 // pack / extract / fill
@@ -147,49 +134,6 @@ __global__ void bb_fill_i32(int* __restrict__ p, int64_t count, int value) {
         p[i] = value;
 }
 
-// ---------------------------------------------------------------------------
-// Addressing.  A lane's window base is the same for every thread of a wave (a
-// wave never spans two lanes), so it is moved to scalar registers and every
-// window access becomes scalar base + 32-bit lane offset (see buf_ld / buf_st).
-// ---------------------------------------------------------------------------
-// Other band pointers are kept in the global address space: generic (flat)
-// accesses would also count against the LDS wait counter, so every LDS wait
-// would wait for outstanding band loads as well.
-template <typename T>
-using gptr = __attribute__((address_space(1))) T*;
-
-template <typename T>
-__device__ __forceinline__ gptr<T> to_global(T* p) { return (gptr<T>)(p); }
-
-template <typename P>
-__device__ __forceinline__ gptr<P> wave_uniform(P* ptr) {
-    const uint64_t v = reinterpret_cast<uint64_t>(ptr);
-    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
-    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
-    return reinterpret_cast<gptr<P>>((static_cast<uint64_t>(hi) << 32) | lo);
-}
-
-// a value known to be equal on every lane of the wave, moved to a scalar register
-__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
-
-// Band stores are made at agent scope: each is coherent across the device once
-// it is acknowledged, so a workgroup releases its results to another one by
-// waiting for its stores (s_waitcnt) and then storing the progress word -- no
-// write-back of the whole L2, which every agent-scope release fence would do.
-template <typename T>
-__device__ __forceinline__ void st_agent(gptr<T> p, T v) {
-    if constexpr (sizeof(T) == 8) {
-        __hip_atomic_store(reinterpret_cast<gptr<unsigned long long>>(p), __builtin_bit_cast(unsigned long long, v),
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else if constexpr (sizeof(T) == 4) {
-        __hip_atomic_store(reinterpret_cast<gptr<unsigned int>>(p), __builtin_bit_cast(unsigned int, v), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-        __hip_atomic_store(reinterpret_cast<gptr<unsigned short>>(p), __builtin_bit_cast(unsigned short, v),
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-}
-
 // Window accesses of the two tasks go through raw buffer instructions: the
 // descriptor holds the wave-uniform window base (scalar registers), each lane
 // adds one 32-bit offset and a wave-uniform stride rides in the scalar offset,
@@ -234,41 +178,6 @@ __device__ __forceinline__ void buf_st(Rsrc r, int voff, int soff, T v) {
     }
 }
 
-
-// ---------------------------------------------------------------------------
-// Householder application to one row / column segment of m+1 values held in
-// registers: a <- a - (tau (a . v)) v.
-//   FP64 storage: the dot is summed left to right with separate multiply and add
-//   and the update is a - (tau w) v, i.e. the same IEEE operations as a plain
-//   sequential implementation (no fused multiply-add; contraction is off).
-//   FP32 / FP16 storage: compensated Dot2 (Ogita, Rump, Oishi 2005) with
-//   TwoSum and an FMA-based TwoProduct, then a - fma(tau w, v).
-// ---------------------------------------------------------------------------
-template <typename C, int TWM>
-__device__ __forceinline__ void apply_segment(C (&av)[TWM + 1], const C (&vs)[TWM + 1], C tau, int m) {
-    if constexpr (std::is_same<C, double>::value) {
-        // entries t > m are +0 in av and vs: they add exactly 0 and stay 0
-        double w = 0.0;
-#pragma unroll
-        for (int t = 0; t <= TWM; ++t) w = w + av[t] * vs[t];
-        const double tw = tau * w;
-#pragma unroll
-        for (int t = 0; t <= TWM; ++t) av[t] = av[t] - tw * vs[t];
-    } else {
-        float s = 0.f, comp = 0.f;
-#pragma unroll
-        for (int t = 0; t <= TWM; ++t) {
-            const float pr = av[t] * vs[t];
-            const float ep = fmaf(av[t], vs[t], -pr);
-            float es;
-            two_sum(s, pr, s, es);
-            comp = comp + (es + ep);
-        }
-        const float tw = tau * (s + comp);
-#pragma unroll
-        for (int t = 0; t <= TWM; ++t) av[t] = fmaf(-tw, vs[t], av[t]);
-    }
-}
 
 // ---------------------------------------------------------------------------
 // Window segment movement.  Entry t of a segment lives at column / row offset
@@ -519,27 +428,6 @@ struct LaneLds {
 // accumulation registers instead of spilling to scratch memory.
 template <int TWM>
 constexpr int max_threads() { return TWM >= 32 ? 256 : (TWM >= 16 ? 512 : 1024); }
-
-// Thread 0 only: spin until *flag >= need (or abort / watchdog).  Returns the value
-// seen (>= need) or -1 on abort; ends with an agent-scope acquire (invalidates this
-// CU's L1 and the stale lines of this XCD's L2).
-__device__ __forceinline__ int poll_ge(const int* flag, int need, int* abort_flag, int* err_word, unsigned spin_limit) {
-    unsigned spins = 0;
-    int v;
-    while ((v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < need) {
-        __builtin_amdgcn_s_sleep(1);
-        if ((++spins & 255u) == 0) {
-            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return -1;
-            if (spins > spin_limit) {
-                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(err_word, 2 /*BB_ERR_TIMEOUT*/, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-                return -1;
-            }
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return v;
-}
 
 // One group of consecutive sweeps r0 .. r0+nl-1 of one stage.
 struct GroupArgs {
