@@ -183,6 +183,11 @@ int bb_sym_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void *band, int6
  * (c >= 1): 2, or 3 when c = 1. */
 int bb_sym_min_lag(int64_t c);
 
+/* Algorithmic bytes of the symmetric chase: read + write of the lower-triangle
+ * entries every step touches (column k's segment, the left-pass columns, the
+ * diagonal block's lower triangle, the right-pass rows), summed over all steps. */
+double bb_sym_model_bytes(int64_t n, int64_t b, int elem_size, int tw);
+
 /*
  * Reduce `count` independent bands of uneven n_i, b_i in one persistent launch
  * that draws (matrix, stage, sweep) tasks from a device work queue.  The paper

@@ -51,6 +51,8 @@ def _load():
     lib.bb_reduce_vectors.restype = ctypes.c_int
     lib.bb_sym_reduce.argtypes = [i64, i64, ctypes.c_int, vp, i64, vp, vp, vp]
     lib.bb_sym_reduce.restype = ctypes.c_int
+    lib.bb_sym_model_bytes.argtypes = [i64, i64, ctypes.c_int, ctypes.c_int]
+    lib.bb_sym_model_bytes.restype = ctypes.c_double
     lib.bb_sym_min_lag.argtypes = [i64]
     lib.bb_sym_min_lag.restype = ctypes.c_int
     lib.bb_reduce_noalloc.argtypes = [i64, i64, ctypes.c_int, vp, i64, vp, vp, vp]
@@ -95,7 +97,7 @@ def _load():
 
 lib = _load()
 
-EXPORTS = ("bb_reduce", "bb_reduce_vectors", "bb_sym_reduce", "bb_sym_min_lag", "bb_reduce_noalloc", "bb_reduce_batched", "bb_set_params", "bb_get_params", "bb_autotune", "bb_autotune_batched", "bb_resolved_params",
+EXPORTS = ("bb_reduce", "bb_reduce_vectors", "bb_sym_reduce", "bb_sym_min_lag", "bb_sym_model_bytes", "bb_reduce_noalloc", "bb_reduce_batched", "bb_set_params", "bb_get_params", "bb_autotune", "bb_autotune_batched", "bb_resolved_params",
            "bb_workspace_bytes", "bb_model_bytes", "bb_plan", "bb_min_lag", "bb_stream_status",
            "bb_release", "bb_error_string", "bb_timing_enable", "bb_timing_read", "bb_bidiag_sigma")
 
@@ -186,6 +188,10 @@ def bb_sym_reduce(band, n: int, b: int, d=None, e=None, stream=None, ldband: int
                            ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(e.data_ptr()), _stream_handle(stream))
     _check(rc, "bb_sym_reduce")
     return d[:n], e[:max(n - 1, 0)]
+
+
+def sym_model_bytes(n: int, b: int, elem_size: int, tw: int) -> float:
+    return float(lib.bb_sym_model_bytes(n, b, elem_size, tw))
 
 
 def sym_min_lag(c: int) -> int:

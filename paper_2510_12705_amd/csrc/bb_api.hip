@@ -585,6 +585,11 @@ static int enqueue_call(const Call& c, const void* band, int64_t ldband, double*
         stage_shape(L, sg, dtype, &ntl_s, &lanes_s);
         const int64_t ngroups = (a.nsweeps + lanes_s - 1) / lanes_s;
         const int grid = (int)std::min<int64_t>(ngroups, (int64_t)ds->cus * L.groups_per_cu);
+        // XCD-aware claims hand group q only to workgroups on XCD (q / xcd_run) mod nxcd,
+        // so every XCD must hold a workgroup: the dispatcher deals workgroups to the XCDs
+        // round-robin, which a grid of at least nxcd guarantees.  A smaller grid (a band
+        // with fewer sweep groups than XCDs) claims in one global order instead.
+        if (grid < a.nxcd) a.nxcd = 0;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         bool timed = false;
         if (timing_allowed) {
@@ -702,6 +707,11 @@ int bb_reduce_vectors(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, 
 }
 
 int bb_sym_min_lag(int64_t c) { return c < 1 ? -1 : (c == 1 ? 3 : 2); }
+
+double bb_sym_model_bytes(int64_t n, int64_t b, int elem_size, int tw) {
+    if (n <= 0 || b < 0 || elem_size <= 0 || tw < 1) return 0.0;
+    return bbp::sym_model_bytes(n, std::min<int64_t>(b, n - 1), elem_size, tw);
+}
 
 // Symmetric band -> tridiagonal: pack the lower band into a working band with
 // room for the bulge fill, one persistent stage kernel per bandwidth-reduction

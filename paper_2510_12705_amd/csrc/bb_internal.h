@@ -20,7 +20,9 @@ struct StageArgs {
     int* abort_flag;    // [1] watchdog abort word (zeroed before launch)
     int* err_word;      // host-mapped error word
     unsigned spin_limit;
-    int nxcd;           // XCDs of the device (0: groups are claimed in one global order)
+    int nxcd;           // XCDs of the device (0: groups are claimed in one global order; the
+                        // host passes 0 when the grid is smaller than the XCD count, since
+                        // XCD-aware claims need a workgroup on every XCD)
     int xcd_run;        // consecutive groups placed on one XCD (>= 1; used when nxcd > 0)
     double* vlog;       // reflector log (null: none): [side][step j][sweep r][wlog] doubles,
                         // side 0 = right (row) reflectors, 1 = left (column) reflectors;

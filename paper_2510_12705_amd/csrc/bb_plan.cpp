@@ -86,6 +86,28 @@ double model_bytes(int64_t n, int64_t b, int elem, int tw) {
     return 2.0 * elems * (double)elem;
 }
 
+// Symmetric chase: per step the lower-triangle entries it reads and writes --
+// column k's segment, rows p..p+m of the columns k+1..p-1, the block's lower
+// triangle, and rows p+m+1..L of columns p..p+m.
+double sym_model_bytes(int64_t n, int64_t b, int elem, int tw) {
+    double elems = 0.0;
+    for (const Stage& s : make_plan(b, tw).stages) {
+        const int64_t bs = s.b, t = s.tw, c = s.c;
+        for (int64_t r = 0; r + c + 1 <= n - 1; ++r) {
+            for (int64_t j = 0;; ++j) {
+                const int64_t p = r + c + j * bs;
+                const int64_t k = j == 0 ? r : p - bs;
+                const int64_t m = j == 0 ? std::min(r + bs, n - 1) - p : std::min(t, n - 1 - p);
+                if (m < 1) break;
+                const int64_t L = std::min(p + m + bs, n - 1);
+                elems += (double)(m + 1) * (double)(p - k) + (double)(m + 1) * (double)(m + 2) / 2.0 +
+                         (double)(L - p - m) * (double)(m + 1);
+            }
+        }
+    }
+    return 2.0 * elems * (double)elem;
+}
+
 namespace {
 std::mutex mu;
 std::map<std::tuple<int, int64_t, int>, Tuned> cache;

@@ -45,6 +45,8 @@ int kernel_twm(int tw);
 
 // Read + write bytes of the L-shaped window of every step, summed.
 double model_bytes(int64_t n, int64_t b, int elem, int tw);
+// The same for the symmetric chase (lower-triangle entries of each step's window).
+double sym_model_bytes(int64_t n, int64_t b, int elem, int tw);
 
 // autotuned parameters per (n bucket, b, dtype); 0 fields mean automatic
 struct Tuned {

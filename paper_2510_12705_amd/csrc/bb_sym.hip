@@ -63,43 +63,78 @@ __global__ void bb_sym_extract(const T* __restrict__ W, int64_t n, int64_t ldw, 
     }
 }
 
-// One step of one sweep, executed by the whole workgroup.
+// One step of one sweep, executed by the whole workgroup.  Every global load of
+// the step is issued at its start, the reflector column first (so the reflector
+// is formed while the others are in flight): thread `tid` holds the column
+// k+1+tid of the left pass and the row p+tid of the right pass (further items,
+// for windows wider than the workgroup, are loaded where they are used), and
+// the block's lower triangle is loaded into registers and mirrored into LDS.
 template <typename T, int TWM>
 __device__ __forceinline__ void sym_step(gptr<T> W, int64_t ldw, int n, int b, int k, int p, int m,
                                          typename Compute<T>::type* blk, double* scr) {
     using C = typename Compute<T>::type;
     constexpr int LDB = TWM + 1;
+    constexpr int NBE = (LDB * LDB + kSymThreads - 1) / kSymThreads;  // block entries per thread
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     auto at = [&](int i, int q) { return W + ((int64_t)(i - q) + (int64_t)q * ldw); };
-    // reflector from A[p..p+m, k] (every wave computes it; FP64 for every storage type)
+    const int nq = p - k - 1;                 // columns k+1 .. p-1 left of the block
+    const int L = min(p + m + b, n - 1);
+    const int nrows = L - p + 1;              // rows p .. L of the right pass
+    const int64_t rs = ldw - 1;               // stride of a row segment
+    // ---- loads ----
     const double xl = static_cast<double>(*at(p + min(lane, m), k));
+    C aL[TWM + 1], aR[TWM + 1];
+    if (tid < nq) {
+        const gptr<T> col = at(p, k + 1 + tid);
+#pragma unroll
+        for (int t = 0; t <= TWM; ++t) aL[t] = to_c(col[min(t, m)]);
+    }
+    if (tid > m && tid < nrows) {
+        const gptr<T> row = at(p + tid, p);
+#pragma unroll
+        for (int t = 0; t <= TWM; ++t) aR[t] = to_c(row[(int64_t)min(t, m) * rs]);
+    }
+    C bv[NBE];
+#pragma unroll
+    for (int z = 0; z < NBE; ++z) {
+        const int e = tid + z * kSymThreads;
+        const int t = e / (m + 1), s = e - t * (m + 1);
+        bv[z] = (e < (m + 1) * (m + 1) && s >= t) ? to_c(*at(p + s, p + t)) : C(0);
+    }
+    // ---- reflector (every wave; FP64 for every storage type) ----
     C vs[TWM + 1];
     double taud, betad, v_own, v_hi;
     house_lds<TWM>(xl, 0.0, m, scr, vs, taud, betad, v_own, v_hi);
     const C tau = static_cast<C>(taud);
-    // the block, mirrored to a full square: blk[s + t * LDB] = A(p+s, p+t)
-    for (int e = tid; e < (m + 1) * (m + 1); e += kSymThreads) {
+    // ---- the block, mirrored to a full square: blk[s + t * LDB] = A(p+s, p+t) ----
+#pragma unroll
+    for (int z = 0; z < NBE; ++z) {
+        const int e = tid + z * kSymThreads;
         const int t = e / (m + 1), s = e - t * (m + 1);
-        const C val = to_c(s >= t ? *at(p + s, p + t) : *at(p + t, p + s));
-        blk[s + t * LDB] = val;
+        if (e < (m + 1) * (m + 1) && s >= t) {
+            blk[s + t * LDB] = bv[z];
+            blk[t + s * LDB] = bv[z];
+        }
     }
     __syncthreads();
-    const int nq = p - k - 1;  // columns k+1 .. p-1 left of the block
-    C av[TWM + 1];
-    // left pass: one thread per column
+    // ---- left pass: one thread per column ----
     for (int ci = tid; ci < nq + m + 1; ci += kSymThreads) {
         if (ci < nq) {
-            const int q = k + 1 + ci;
-            const gptr<T> col = at(p, q);
+            const gptr<T> col = at(p, k + 1 + ci);
+            if (ci != tid) {
 #pragma unroll
-            for (int t = 0; t <= TWM; ++t) av[t] = t <= m ? to_c(col[t]) : C(0);
-            if (taud != 0.0) apply_segment<C, TWM>(av, vs, tau, m);
+                for (int t = 0; t <= TWM; ++t) aL[t] = to_c(col[min(t, m)]);
+            }
+#pragma unroll
+            for (int t = 0; t <= TWM; ++t) aL[t] = t <= m ? aL[t] : C(0);
+            if (taud != 0.0) apply_segment<C, TWM>(aL, vs, tau, m);
 #pragma unroll
             for (int t = 0; t <= TWM; ++t)
-                if (t <= m) st_agent(col + t, static_cast<T>(av[t]));
+                if (t <= m) st_agent(col + t, static_cast<T>(aL[t]));
         } else {
             const int t2 = ci - nq;
+            C av[TWM + 1];
 #pragma unroll
             for (int t = 0; t <= TWM; ++t) av[t] = t <= m ? blk[t + t2 * LDB] : C(0);
             if (taud != 0.0) apply_segment<C, TWM>(av, vs, tau, m);
@@ -109,11 +144,10 @@ __device__ __forceinline__ void sym_step(gptr<T> W, int64_t ldw, int n, int b, i
         }
     }
     __syncthreads();
-    // right pass: one thread per row (the block's rows, then rows p+m+1 .. L)
-    const int L = min(p + m + b, n - 1);
-    const int nrows = L - p + 1;
+    // ---- right pass: one thread per row (the block's rows, then rows p+m+1 .. L) ----
     for (int ri = tid; ri < nrows; ri += kSymThreads) {
         if (ri <= m) {
+            C av[TWM + 1];
 #pragma unroll
             for (int t = 0; t <= TWM; ++t) av[t] = t <= m ? blk[ri + t * LDB] : C(0);
             if (taud != 0.0) apply_segment<C, TWM>(av, vs, tau, m);
@@ -121,21 +155,26 @@ __device__ __forceinline__ void sym_step(gptr<T> W, int64_t ldw, int n, int b, i
             for (int t = 0; t <= TWM; ++t)
                 if (t <= m) blk[ri + t * LDB] = av[t];
         } else {
-            const int i = p + ri;
-            const gptr<T> row = at(i, p);  // A(i, p + t) = row[t * (ldw - 1)]
+            const gptr<T> row = at(p + ri, p);  // A(p + ri, p + t) = row[t * rs]
+            if (ri != tid) {
 #pragma unroll
-            for (int t = 0; t <= TWM; ++t) av[t] = t <= m ? to_c(row[(int64_t)t * (ldw - 1)]) : C(0);
-            if (taud != 0.0) apply_segment<C, TWM>(av, vs, tau, m);
+                for (int t = 0; t <= TWM; ++t) aR[t] = to_c(row[(int64_t)min(t, m) * rs]);
+            }
+#pragma unroll
+            for (int t = 0; t <= TWM; ++t) aR[t] = t <= m ? aR[t] : C(0);
+            if (taud != 0.0) apply_segment<C, TWM>(aR, vs, tau, m);
 #pragma unroll
             for (int t = 0; t <= TWM; ++t)
-                if (t <= m) st_agent(row + (int64_t)t * (ldw - 1), static_cast<T>(av[t]));
+                if (t <= m) st_agent(row + (int64_t)t * rs, static_cast<T>(aR[t]));
         }
     }
     __syncthreads();
-    // the block's lower triangle goes back; column k becomes (beta, 0, ..., 0)
-    for (int e = tid; e < (m + 1) * (m + 1); e += kSymThreads) {
+    // ---- the block's lower triangle goes back; column k becomes (beta, 0, ..., 0) ----
+#pragma unroll
+    for (int z = 0; z < NBE; ++z) {
+        const int e = tid + z * kSymThreads;
         const int t = e / (m + 1), s = e - t * (m + 1);
-        if (s >= t) st_agent(at(p + s, p + t), static_cast<T>(blk[s + t * LDB]));
+        if (e < (m + 1) * (m + 1) && s >= t) st_agent(at(p + s, p + t), static_cast<T>(blk[s + t * LDB]));
     }
     if (tid <= m) st_agent(at(p + tid, k), static_cast<T>(tid == 0 ? betad : 0.0));
 }

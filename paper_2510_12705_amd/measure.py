@@ -3,6 +3,7 @@
     python -m paper_2510_12705_amd.measure c4   # n = 16384, b = 16 .. 256, FP64 / FP32 / FP16 storage
     python -m paper_2510_12705_amd.measure c5   # 512 ragged FP32 bands: one batched call vs a loop
     python -m paper_2510_12705_amd.measure sigma  # sigma of the n = 32768 bidiagonal on the device
+    python -m paper_2510_12705_amd.measure sym    # symmetric band -> tridiagonal, FP64 / FP32 storage
 
 Each case is timed as the best of two runs after one warm-up (host wall clock
 around the call and a device synchronisation), in the default launch
@@ -108,6 +109,27 @@ def ragged_batch(count=512, seed=5):
     bb.release()
 
 
+def symmetric(cases=((8192, 64), (32768, 128))):
+    """The symmetric band -> tridiagonal reduction (bb_sym_reduce), FP64 and FP32
+    storage, N(0,1) lower bands: time and % of roofline by the symmetric
+    algorithmic bytes at the one-cache-line tilewidth."""
+    import torch
+
+    from . import bb
+    bb.reset_params()
+    for n, b in cases:
+        rng = np.random.default_rng(n + b)
+        band = torch.from_numpy(rng.standard_normal((n, b + 1))).cuda()
+        out = []
+        for dt, elem in ((torch.float64, 8), (torch.float32, 4)):
+            t = band.to(dt)
+            ms = _best_ms(torch, lambda: bb.bb_sym_reduce(t, n, b))
+            alg = bb.sym_model_bytes(n, b, elem, TW_REF[elem])
+            out.append("%s %.1f ms (%.1f%% roofline)" % (str(dt).split(".")[-1], ms,
+                                                           100 * alg / (ms / 1e3) / PEAK_BYTES_PER_S))
+        print("symmetric n=%d b=%d: %s" % (n, b, " | ".join(out)), flush=True)
+
+
 def bidiag_sigma(n=32768, b=128):
     """sigma of the bidiagonal that the n = 32768, b = 128 reduction returns: the device
     bisection (bb_bidiag_sigma) against LAPACK dsterf on the host (one core), the
@@ -142,4 +164,4 @@ def bidiag_sigma(n=32768, b=128):
 
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "c4"
-    {"c4": bandwidth_sweep, "c5": ragged_batch, "sigma": bidiag_sigma}[what]()
+    {"c4": bandwidth_sweep, "c5": ragged_batch, "sigma": bidiag_sigma, "sym": symmetric}[what]()

@@ -209,6 +209,24 @@ def test_edge_cases(bb):
     assert np.array_equal(d2.cpu().numpy(), d1) and np.array_equal(e2.cpu().numpy(), e1)
 
 
+def test_tiny_bands_with_fewer_sweep_groups_than_xcds(bb):
+    """Bands with fewer sweep groups than the device has XCDs launch fewer workgroups
+    than XCDs; they must still process every group.  Workgroups of small launches land
+    on XCDs that depend on the launches before them, so each case follows a device
+    kernel of a different size."""
+    _say("case tiny bands, varied dispatch history")
+    bb.reset_params()
+    rng = np.random.default_rng(17)
+    for trial in range(40):
+        n = int(rng.integers(3, 14))
+        b = int(rng.integers(2, n + 2))
+        band = inputs.band_normal(n, b, seed=100 + trial)
+        _ = torch.ones(int(rng.integers(1, 64)) * 256 * 7, device="cuda").sum()  # a launch of another size
+        d, e = gpu_reduce(bb, band, n, b)
+        do, eo = oracle.reduce(band, n, b, bb.resolved_params(n, b, bb.F64).tw)
+        assert np.array_equal(d, do) and np.array_equal(e, eo), (trial, n, b)
+
+
 @pytest.mark.parametrize("n,b,tw", [(200, 8, 3), (500, 33, 16)])
 def test_bidiagonal_input_unchanged(bb, n, b, tw):
     rng = np.random.default_rng(11)

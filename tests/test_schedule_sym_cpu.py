@@ -83,3 +83,26 @@ def test_sym_lag_is_safe_and_tight(n, b, tw):
     assert H == (3 if c == 1 else 2)
     assert unordered_conflicts(n, b, tw, H) == 0
     assert unordered_conflicts(n, b, tw, H - 1) > 0
+
+
+def _py_sym_model_bytes(n, b, elem, tw):
+    tot = 0
+    bq = min(b, n - 1)
+    while bq > 1:
+        t = min(tw, bq - 1)
+        c = bq - t
+        for r in range(n - c - 1):
+            j = 0
+            while True:
+                w = window(n, bq, t, c, r, j)
+                if w is None:
+                    break
+                tot += len(w)
+                j += 1
+        bq = c
+    return 2.0 * tot * elem
+
+
+@pytest.mark.parametrize("n,b,tw,elem", [(60, 7, 3, 8), (45, 12, 12, 4), (30, 3, 1, 8), (25, 30, 8, 8)])
+def test_sym_model_bytes_counts_every_window_entry(n, b, tw, elem):
+    assert bb.sym_model_bytes(n, b, elem, tw) == pytest.approx(_py_sym_model_bytes(n, b, elem, tw), rel=1e-12)
