@@ -43,7 +43,7 @@ def build(force: bool = True) -> str:
     os.makedirs(os.path.dirname(_LIB), exist_ok=True)
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fopenmp",
                                "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -62,6 +62,9 @@ def _load():
         lib.bbo_reduce_pipelined.argtypes = [i64, i64, i64, dp, i64, dp, dp,
                                              ctypes.POINTER(ctypes.c_int), ctypes.c_uint64]
         lib.bbo_reduce_pipelined.restype = ctypes.c_int
+        lib.bbo_reduce_wavefront.argtypes = [i64, i64, i64, dp, i64, dp, dp, ctypes.POINTER(ctypes.c_int),
+                                             ctypes.c_int, i64, i64, ctypes.POINTER(ctypes.c_int)]
+        lib.bbo_reduce_wavefront.restype = ctypes.c_int
         lib.bbo_nrm2.argtypes = [dp, i64]
         lib.bbo_nrm2.restype = ctypes.c_double
         lib.bbo_sym_reduce.argtypes = [i64, i64, i64, dp, i64, dp, dp, dp]
@@ -148,6 +151,29 @@ def reduce_pipelined(band: np.ndarray, n: int, b: int, tw: int, lag, seed: int):
     if rc != 0:
         raise RuntimeError("bbo_reduce_pipelined failed with code %d" % rc)
     return d[:n], e[:max(n - 1, 0)]
+
+
+# Half-step lags of the dependency rule (Sec. III-A): H for c == 1, c == 2, c >= 3.
+DEFAULT_LAG = (4, 3, 2)
+
+
+def reduce_wavefront(band: np.ndarray, n: int, b: int, tw: int, threads: int = 0, group: int = 1,
+                     lag=DEFAULT_LAG, max_stages: int = 0):
+    """The reduction as a wavefront over host threads (the multi-core CPU
+    baseline), ``group`` consecutive sweeps per thread at a time; bitwise equal
+    to ``reduce``.  ``max_stages`` > 0 stops after that many stages (a timing
+    sample).  Returns (d, e, threads used)."""
+    lib = _load()
+    band = np.ascontiguousarray(band, dtype=np.float64)
+    d = np.zeros(max(n, 1))
+    e = np.zeros(max(n - 1, 1))
+    lg = (ctypes.c_int * 3)(*[int(x) for x in lag])
+    used = ctypes.c_int(0)
+    rc = lib.bbo_reduce_wavefront(n, b, tw, _dp(band), band.shape[1], _dp(d), _dp(e), lg, int(threads),
+                                  int(group), int(max_stages), ctypes.byref(used))
+    if rc != 0:
+        raise ValueError("bbo_reduce_wavefront failed with code %d" % rc)
+    return d[:n], e[:max(n - 1, 0)], used.value
 
 
 # ----------------------------------------------------------------------------

@@ -5,8 +5,9 @@
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
  * calls this file; only the test-suite, the smoke check and the CPU-baseline
  * leg of the benchmark do.  It shares no code, header or table with the GPU
- * path.  Build: gcc -O2 -ffp-contract=off -shared -fPIC (no FMA contraction,
- * so every sum is evaluated left to right exactly as written).
+ * path.  Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no FMA
+ * contraction, so every sum is evaluated left to right exactly as written;
+ * OpenMP only for the wavefront timing variant).
  *
  * What it computes (paper: Sec. III, Algorithm 1 and its description; the
  * dependency discussion in Sec. III-A; the storage paragraph of Sec. IV):
@@ -37,7 +38,10 @@
  *   and H = I - tau v v^T maps x to beta e1.  The annihilated entries are
  *   written as exact zeros and beta is stored in place.
  */
+#define _POSIX_C_SOURCE 200809L
 #include <math.h>
+#include <omp.h>
+#include <sched.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -345,6 +349,110 @@ int bbo_reduce_pipelined(int64_t n, int64_t b, int64_t TW, const double *band, i
     if (rc == 0) extract(&A, d, e);
     free(len); free(prog); free(ready); free(A.w);
     return rc;
+}
+
+/*
+ * Wavefront execution on host threads: the multi-core CPU timing baseline.
+ * The rule of bbo_reduce_pipelined run for real, with consecutive sweeps
+ * bundled into groups of G so that the windows one thread loads are reused by
+ * the G sweeps of its group before another core needs them.  Within a stage,
+ * threads claim groups in increasing order from a shared counter.  A thread
+ * passes over its group's sweeps in order again and again, running the next
+ * half-step h of every sweep whose predecessor allows it: sweep r-1 has
+ * completed h+H half-steps, or it and every sweep before it has finished.  For
+ * the group's first sweep the predecessor is the last sweep of the previous
+ * group, whose progress that group's thread publishes (release store after the
+ * half-step's writes, acquire load by the reader); a group publishes DONE once
+ * all its sweeps have finished and the previous group is DONE.  Stages are
+ * separated by the end of the parallel region.  Lower groups never wait on
+ * higher ones, so the scheme cannot deadlock, and every order it allows gives
+ * results bitwise those of bbo_reduce().  G = 1 is the plain one-sweep-per-
+ * thread wavefront.  nthreads <= 0 takes OpenMP's default.  max_stages > 0
+ * stops after that many stages (a timing sample; d and e are then the
+ * diagonal and super-diagonal of a band that is not yet bidiagonal).  Returns
+ * as bbo_reduce; *threads_used (if not NULL) receives the team size.
+ */
+#define BBO_MAXGROUP 256
+
+static void wait_progress(const int64_t *w, int64_t target) {
+    unsigned spins = 0;
+    while (__atomic_load_n(w, __ATOMIC_ACQUIRE) < target) {
+        if (++spins > 4096) { sched_yield(); spins = 0; }
+    }
+}
+
+int bbo_reduce_wavefront(int64_t n, int64_t b, int64_t TW, const double *band, int64_t ldband,
+                         double *d, double *e, const int *lag, int nthreads, int64_t G, int64_t max_stages,
+                         int *threads_used) {
+    if (G < 1 || G > BBO_MAXGROUP) return -10;
+    bbo_band A;
+    int64_t tw0;
+    int rc = setup(n, &b, TW, band, ldband, &A, &tw0);
+    if (rc) return rc;
+    const bbo_opts o = {0};
+    const int64_t DONE = INT64_MAX;
+    enum { PAD = 16 };   /* one progress word per 128 bytes: spinning readers do not share a line */
+    const int64_t ngmax = n / G + 2;
+    int64_t *pub = (int64_t *)calloc((size_t)ngmax * PAD, sizeof(int64_t));
+    if (!pub) { free(A.w); return 1; }
+    int team = 1;
+    int64_t bs = b;
+    for (int64_t stage = 0; bs > 1 && (max_stages <= 0 || stage < max_stages); ++stage) {
+        const int64_t tw = TW < bs - 1 ? TW : bs - 1, c = bs - tw;
+        const int64_t H = c == 1 ? lag[0] : (c == 2 ? lag[1] : lag[2]);
+        const int64_t ns = n - 1 - c > 0 ? n - 1 - c : 0;   /* sweeps r with r + c + 1 <= n - 1 */
+        const int64_t ng = (ns + G - 1) / G;
+        for (int64_t g = 0; g < ng; ++g) pub[g * PAD] = 0;
+        int64_t next = 0;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : omp_get_max_threads())
+        {
+#pragma omp single
+            team = omp_get_num_threads();
+            int64_t lp[BBO_MAXGROUP];   /* half-steps completed by each sweep of the group */
+            for (;;) {
+                const int64_t g = __atomic_fetch_add(&next, 1, __ATOMIC_RELAXED);
+                if (g >= ng) break;
+                const int64_t r0 = g * G, gs = ns - r0 < G ? ns - r0 : G;
+                int64_t fin = 0;   /* sweeps r0 .. r0+fin-1 have finished */
+                for (int64_t i = 0; i < gs; ++i) lp[i] = 0;
+                while (fin < gs) {
+                    int moved = 0;
+                    for (int64_t i = fin; i < gs; ++i) {
+                        const int64_t r = r0 + i, h = lp[i];
+                        int64_t k, p, m = step_geom(n, bs, tw, c, r, h / 2, &k, &p);
+                        if (m < 1) {   /* finished; the finished prefix only grows in order */
+                            if (i == fin) ++fin;
+                            continue;
+                        }
+                        /* may half-step h of sweep r run? */
+                        int ok;
+                        if (i == 0) {
+                            ok = g == 0 || __atomic_load_n(&pub[(g - 1) * PAD], __ATOMIC_ACQUIRE) >= h + H;
+                        } else {
+                            ok = lp[i - 1] >= h + H;
+                            if (!ok && fin >= i)   /* every earlier sweep of the group finished */
+                                ok = g == 0 || __atomic_load_n(&pub[(g - 1) * PAD], __ATOMIC_ACQUIRE) == DONE;
+                        }
+                        if (!ok) continue;
+                        if (h % 2 == 0) task_right(&A, k, p, m, &o, NULL, 0);
+                        else task_left(&A, bs, p, m, &o, NULL, 0);
+                        lp[i] = h + 1;
+                        moved = 1;
+                        if (i == gs - 1) __atomic_store_n(&pub[g * PAD], h + 1, __ATOMIC_RELEASE);
+                    }
+                    if (!moved && fin < gs) sched_yield();
+                }
+                if (g > 0) wait_progress(&pub[(g - 1) * PAD], DONE);
+                __atomic_store_n(&pub[g * PAD], DONE, __ATOMIC_RELEASE);
+            }
+        }
+        bs = c;
+    }
+    extract(&A, d, e);
+    if (threads_used) *threads_used = team;
+    free(pub);
+    free(A.w);
+    return 0;
 }
 
 /*

@@ -194,6 +194,37 @@ def test_pipelined_order_is_bitwise_sequential(n, b, tw):
         assert np.array_equal(d, d0) and np.array_equal(e, e0)
 
 
+@pytest.mark.parametrize("n,b,tw,threads,group", [(40, 8, 2, 4, 1), (300, 17, 4, 8, 1), (257, 33, 16, 3, 3),
+                                                  (200, 64, 32, 8, 8), (64, 5, 1, 8, 2), (300, 9, 4, 8, 5),
+                                                  (100, 3, 1, 4, 256), (3, 2, 1, 2, 1), (1, 4, 4, 2, 4)])
+def test_wavefront_threads_are_bitwise_sequential(n, b, tw, threads, group):
+    """The multi-threaded wavefront (the CPU timing baseline) runs the same
+    half-steps under the lag rule on real threads, one sweep or a group of
+    sweeps per thread at a time: bitwise the sequential oracle."""
+    band = inputs.band_normal(n, b, seed=n + b)
+    d0, e0 = oracle.reduce(band, n, b, tw)
+    for _ in range(3):
+        d, e, used = oracle.reduce_wavefront(band, n, b, tw, threads=threads, group=group)
+        assert used == (threads if b > 1 and n > 2 else 1)   # no stage runs: no team
+        assert np.array_equal(d, d0) and np.array_equal(e, e0)
+
+
+def test_wavefront_stage_limit_matches_a_one_stage_reduction():
+    """With b = tw + 1 the first stage is the whole reduction, so a one-stage
+    sample must equal the full sequential result; with two stages it must not
+    reach it (the sample really stops)."""
+    n, b, tw = 120, 9, 8
+    band = inputs.band_normal(n, b, seed=4)
+    d0, e0 = oracle.reduce(band, n, b, tw)
+    d, e, _ = oracle.reduce_wavefront(band, n, b, tw, threads=4, group=2, max_stages=1)
+    assert np.array_equal(d, d0) and np.array_equal(e, e0)
+    d0, e0 = oracle.reduce(band, n, b, 4)   # 9 -> 5 -> 1
+    d, e, _ = oracle.reduce_wavefront(band, n, b, 4, threads=4, group=2, max_stages=1)
+    assert not np.array_equal(e, e0)
+    d, e, _ = oracle.reduce_wavefront(band, n, b, 4, threads=4, group=2, max_stages=2)
+    assert np.array_equal(d, d0) and np.array_equal(e, e0)
+
+
 def test_pipelined_detects_unsafe_rule():
     """Planted mistake: a lag one half-step too short must change the result for some order."""
     n, b, tw = 40, 8, 2   # c = 6 >= 3, safe lag 2, unsafe lag 1
