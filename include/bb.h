@@ -215,13 +215,15 @@ int bb_reduce_batched(int64_t count, const int64_t *n, const int64_t *b, bb_dtyp
  * returns (the paper computes them on the CPU, Sec. V-A; this is the on-device
  * alternative).  sigma(B) are the non-negative eigenvalues of the 2n x 2n
  * Golub-Kahan tridiagonal (zero diagonal, off-diagonal d0, e0, d1, ..., d_{n-1});
- * one thread finds each by bisection on the Sturm count of that matrix, to an
- * absolute accuracy of about 4 eps sigma_i + 2^-60 ||B||.
+ * a group of four threads finds each by multisection on the Sturm count of
+ * that matrix (the signs of its leading minors, on B scaled by a power of two),
+ * to an absolute accuracy of about 4 eps sigma_i + 2^-60 ||B||.
  *   n        order (0 <= n <= 2^29).
  *   d, e     device pointers to n and max(n - 1, 0) doubles (e may be NULL if n <= 1).
  *   sigma    device pointer to n doubles: sigma_0 >= sigma_1 >= ... >= 0 (output).
  *   stream   hipStream_t.  Asynchronous; allocates nothing.
- * Argument numbers for -i: n=1, d=2, e=3, sigma=4.  NaN input gives NaN output.
+ * Argument numbers for -i: n=1, d=2, e=3, sigma=4.  A NaN or infinite entry
+ * makes every output NaN.
  */
 int bb_bidiag_sigma(int64_t n, const double *d, const double *e, double *sigma, void *stream);
 

@@ -151,11 +151,16 @@ def bidiag_sigma(n=32768, b=128):
     w, info = lapack.dsterf(np.zeros(2 * n), off)
     host_ms = (time.perf_counter() - t) * 1e3
     ref = np.sort(w)[::-1][:n].clip(min=0.0)
-    # Sturm-count work: 4 lanes per value, ~26 multisection steps (each divides the
-    # interval by 5 down to 2^-60 of the bound), 2n pivots of one division and two
-    # multiply-adds per count
-    evals = 4 * 26
-    flops = float(n) * evals * 2 * n * 4
+    # Sturm-count work: the coarse pass counts at 4n points; then value j takes
+    # ceil(log_9(cell / max(4 eps sigma_j, 2^-60 hi0))) steps of 8 counts from its
+    # cell (width hi0 / 3n); a count is 2n - 1 steps of one multiply and one
+    # multiply-add per point plus the shared square of the entry (about 4 flops)
+    off_abs = np.abs(off)
+    hi0 = np.max(np.concatenate([off_abs[:1], off_abs[1:] + off_abs[:-1], off_abs[-1:]])) * (1 + 4 * 2.0 ** -52)
+    stop = np.maximum(4 * 2.0 ** -52 * sig, 2.0 ** -60 * hi0)
+    iters = np.maximum(np.ceil(np.log((hi0 / (3 * n)) / stop) / np.log(9.0)), 0)
+    counts = 4.0 * n + 8.0 * float(np.sum(iters))
+    flops = counts * (2 * n - 1) * 4
     print("n=%d: device multisection %.1f ms (%.0f GFLOP/s of Sturm counts), host dsterf %.1f ms (%.0fx); "
           "max |sigma_dev - sigma_dsterf| / sigma_max = %.2e" % (
               n, ms, flops / (ms / 1e3) / 1e9, host_ms, host_ms / ms, np.max(np.abs(sig - ref)) / ref[0]),

@@ -380,6 +380,48 @@ def test_bidiag_sigma_special_cases(bb):
     assert abs(s[0] - smax) <= 8 * EPS64 * smax and abs(s[1] - det / smax) <= 8 * EPS64 * smax
 
 
+def test_bidiag_sigma_power_of_two_scaling_is_exact(bb):
+    """The count runs on the matrix scaled by a power of two (max |b| in [1/2, 1)),
+    so sigma(2^k B) is 2^k sigma(B) bit for bit, also where the squares of the
+    unscaled entries would overflow (k = 600, 1000) or underflow (k = -600, -1000)."""
+    _say("case bidiag sigma 2^k scaling")
+    rng = np.random.default_rng(11)
+    n = 777
+    d = 2.0 + np.abs(rng.standard_normal(n))     # well conditioned: no sigma near the underflow range
+    e = 0.5 * rng.standard_normal(n - 1)
+    s0 = _gpu_sigma(bb, d, e)
+    _check_sigma(bb, d, e)
+    for k in (600, -600, 1000, -1000):
+        s = _gpu_sigma(bb, np.ldexp(d, k), np.ldexp(e, k))
+        assert np.array_equal(s, np.ldexp(s0, k)), k
+
+
+def test_bidiag_sigma_graded_diagonal_relative_accuracy(bb):
+    """A diagonal B whose entries fall from 2 to 2^-8 (the range in which the stop
+    at 4 eps of the interval's upper end, not the 2^-60 ||B|| floor, decides):
+    every sigma is some |d_i|, found to a few ulps of itself."""
+    _say("case bidiag sigma graded diagonal")
+    n = 500
+    rng = np.random.default_rng(12)
+    d = np.ldexp(1.0 + rng.random(n), -(np.arange(n) * 9) // n) * np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    s = _gpu_sigma(bb, d, np.zeros(n - 1))
+    ref = np.sort(np.abs(d))[::-1]
+    assert np.all(np.abs(s - ref) <= 8 * EPS64 * ref), np.max(np.abs(s - ref) / ref)
+
+
+def test_bidiag_sigma_non_finite_input_gives_nan(bb):
+    _say("case bidiag sigma non-finite input")
+    d = np.ones(10)
+    e = np.full(9, 0.5)
+    for bad in (np.nan, np.inf, -np.inf):
+        d2 = d.copy()
+        d2[3] = bad
+        assert np.all(np.isnan(_gpu_sigma(bb, d2, e)))
+        e2 = e.copy()
+        e2[8] = bad
+        assert np.all(np.isnan(_gpu_sigma(bb, d, e2)))
+
+
 def test_bidiag_sigma_after_reduction(bb):
     """The full second + third stage on the device: reduce the n = 8192, b = 64 band,
     then sigma of the result, against the oracle's sigma of the same (d, e) and, through
