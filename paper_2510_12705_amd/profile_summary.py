@@ -1,7 +1,8 @@
 """Summarise rocprofv3 CSV output of ``bench.py`` runs into the text files kept
 under ``profiles/``.
 
-  python -m paper_2510_12705_amd.profile_summary trace <kernel_stats.csv> <kernel_trace.csv> <out.md> "<command>"
+  python -m paper_2510_12705_amd.profile_summary trace <kernel_stats.csv> <kernel_trace.csv> <out.md> "<command>" \
+      [<kernel-name filter for the dispatch table, default bb_stage>]
   python -m paper_2510_12705_amd.profile_summary traffic <fetch_counter_collection.csv> <write_counter_collection.csv> \
       <out.json> <workload> <dtype> "<fetch command>" "<write command>" <copy MiB>
   python -m paper_2510_12705_amd.profile_summary counters <sq_counter_collection.csv> <tcc_counter_collection.csv> \
@@ -26,7 +27,7 @@ def _rows(path):
         return list(csv.DictReader(f))
 
 
-def trace(stats_csv, trace_csv, out_md, command):
+def trace(stats_csv, trace_csv, out_md, command, kernel="bb_stage"):
     stats = _rows(stats_csv)
     tr = _rows(trace_csv)
     lines = ["# rocprofv3 kernel trace: %s" % out_md.rsplit("/", 1)[-1].replace(".md", ""), "",
@@ -37,17 +38,19 @@ def trace(stats_csv, trace_csv, out_md, command):
         lines.append("| `%s` | %s | %.3f | %.3f | %.3f | %.3f | %.2f |" % (
             r["Name"][:90], r["Calls"], float(r["TotalDurationNs"]) / 1e6, float(r["AverageNs"]) / 1e6,
             float(r["MinNs"]) / 1e6, float(r["MaxNs"]) / 1e6, float(r["Percentage"])))
-    lines += ["", "## stage-kernel dispatches (one per bandwidth-reduction stage)", "",
+    lines += ["", "## dispatches of the kernels named `%s`" % kernel, "",
               "| dispatch | kernel | ms | workgroups | threads/WG | VGPRs | LDS bytes | scratch |",
               "|---:|---|---:|---:|---:|---:|---:|---:|"]
     for r in tr:
-        if "bb_stage" not in r["Kernel_Name"]:
+        if kernel not in r["Kernel_Name"]:
             continue
         ms = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
         wg = int(r["Workgroup_Size_X"])
         lines.append("| %s | `%s` | %.3f | %d | %d | %s | %s | %s |" % (
             r["Dispatch_Id"], r["Kernel_Name"][:60], ms, int(r["Grid_Size_X"]) // max(wg, 1), wg, r["VGPR_Count"],
             r["LDS_Block_Size"], r["Scratch_Size"]))
+    lines += ["", "LDS bytes is the static LDS segment as rocprofv3 reports it; LDS requested at launch",
+              "(dynamic shared memory) is not included."]
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
 
@@ -113,7 +116,7 @@ def counters(sq_csv, tcc_csv, out_md, sq_cmd, tcc_cmd, simds=1024):
 
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
-        trace(*sys.argv[2:6])
+        trace(*sys.argv[2:7])
     elif sys.argv[1] == "traffic":
         traffic(*sys.argv[2:10])
     elif sys.argv[1] == "counters":
