@@ -17,7 +17,6 @@ scaled by the ratio of the algorithmic bytes of all stages to that stage's.
 from __future__ import annotations
 
 import argparse
-import glob
 import hashlib
 import json
 import os
@@ -32,9 +31,14 @@ PEAK_HBM_GBPS = 8000.0
 TW_REF = {8: 16, 4: 32, 2: 64}   # one 128-byte line of the storage type
 
 
+# the sources that build the band -> bidiagonal stage kernel and choose its launch
+STAGE_SOURCES = ("bb_api.hip", "bb_device.h", "bb_internal.h", "bb_kernels.hip", "bb_plan.cpp", "bb_plan.h",
+                 "bb_window.h")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2510_12705_amd", "csrc", "*"))):
+    for p in sorted(os.path.join(ROOT, "paper_2510_12705_amd", "csrc", f) for f in STAGE_SOURCES):
         with open(p, "rb") as f:
             h.update(os.path.basename(p).encode())
             h.update(f.read())

@@ -747,7 +747,8 @@ int bb_sym_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, int6
     int* counters = reinterpret_cast<int*>(W + band_bytes);
     rc = check_hip(bbk::launch_fill(counters, per_stage * std::max(nstages, 1), 0, st));
     if (!rc) rc = check_hip(bbk::launch_sym_pack(dtype, band, ldband, n, bb, W, ldw, st));
-    const int gpc = prm.groups_per_cu ? prm.groups_per_cu : 2;
+    // one 512-thread workgroup fits a CU (the FP64 32-wide step uses 240 registers per lane)
+    const int gpc = prm.groups_per_cu ? prm.groups_per_cu : 1;
     if (bb > 1) {
         int s = 0;
         for (bbp::Stage sg = bbp::stage_first(bb, tw); !rc; sg = bbp::stage_next(sg, tw), ++s) {

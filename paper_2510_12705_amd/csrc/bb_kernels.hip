@@ -134,51 +134,6 @@ __global__ void bb_fill_i32(int* __restrict__ p, int64_t count, int value) {
         p[i] = value;
 }
 
-// Window accesses of the two tasks go through raw buffer instructions: the
-// descriptor holds the wave-uniform window base (scalar registers), each lane
-// adds one 32-bit offset and a wave-uniform stride rides in the scalar offset,
-// so a whole row or column segment needs one address register.  Offsets are in
-// elements; the host keeps every in-window byte offset below 2^32, inside the
-// descriptor's range.  Stores carry the agent-scope coherence bit (sc1), the
-// same cache policy as st_agent.
-using Rsrc = __amdgpu_buffer_rsrc_t;
-constexpr int kBufDword3 = 0x00020000;  // gfx9 raw buffer: 32-bit data format, no swizzle
-constexpr int kCpolSc1 = 16;            // cache-policy operand: sc1
-
-template <typename T>
-__device__ __forceinline__ Rsrc make_rsrc(gptr<T> base) {
-    void* generic = reinterpret_cast<void*>(__builtin_bit_cast(uint64_t, base));
-    return __builtin_amdgcn_make_buffer_rsrc(generic, (short)0, -1, kBufDword3);
-}
-
-template <typename T>
-__device__ __forceinline__ T buf_ld(Rsrc r, int voff, int soff) {
-    const int vb = (int)(static_cast<uint32_t>(voff) * static_cast<uint32_t>(sizeof(T)));
-    const int sb = (int)(static_cast<uint32_t>(soff) * static_cast<uint32_t>(sizeof(T)));
-    if constexpr (sizeof(T) == 8) {
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, vb, sb, 0));
-    } else if constexpr (sizeof(T) == 4) {
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, vb, sb, 0));
-    } else {
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, vb, sb, 0));
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void buf_st(Rsrc r, int voff, int soff, T v) {
-    const int vb = (int)(static_cast<uint32_t>(voff) * static_cast<uint32_t>(sizeof(T)));
-    const int sb = (int)(static_cast<uint32_t>(soff) * static_cast<uint32_t>(sizeof(T)));
-    if constexpr (sizeof(T) == 8) {
-        using V2 = __attribute__((ext_vector_type(2))) unsigned int;
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, vb, sb, kCpolSc1);
-    } else if constexpr (sizeof(T) == 4) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, vb, sb, kCpolSc1);
-    } else {
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, vb, sb, kCpolSc1);
-    }
-}
-
-
 // ---------------------------------------------------------------------------
 // Window segment movement.  Entry t of a segment lives at column / row offset
 // min(t, m) (always inside the window); entries t > m are masked to 0 on load,

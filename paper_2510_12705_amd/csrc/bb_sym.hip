@@ -30,15 +30,18 @@
 
 namespace bbk {
 
-constexpr int kSymThreads = 256;
+constexpr int kSymThreads = 512;
+constexpr int kSymHalf = kSymThreads / 2;  // threads of the left group (the right group: the rest)
 
-// LDS of one workgroup: the (TWM+1)^2 block (full square, compute type) and a
-// reflector scratch of 2 (TWM+1) doubles per wave.
+// LDS of one workgroup: the (TWM+1)^2 block (full square, compute type), one
+// staging block of kWave columns of TWM+1 entries per wave of the left group,
+// and a reflector scratch of 2 (TWM+1) doubles per wave.
 template <typename C, int TWM>
 struct SymLds {
     static constexpr int LDB = TWM + 1;
     static constexpr size_t block = 0;
-    static constexpr size_t scratch = (sizeof(C) * LDB * LDB + 15) / 16 * 16;
+    static constexpr size_t stage = (sizeof(C) * LDB * LDB + 15) / 16 * 16;
+    static constexpr size_t scratch = stage + sizeof(C) * kSymHalf * LDB;
     static constexpr size_t scratch_per_wave = sizeof(double) * 2 * LDB;
     static constexpr size_t bytes = scratch + scratch_per_wave * (kSymThreads / kWave);
 };
@@ -63,37 +66,47 @@ __global__ void bb_sym_extract(const T* __restrict__ W, int64_t n, int64_t ldw, 
     }
 }
 
-// One step of one sweep, executed by the whole workgroup.  Every global load of
-// the step is issued at its start, the reflector column first (so the reflector
-// is formed while the others are in flight): thread `tid` holds the column
-// k+1+tid of the left pass and the row p+tid of the right pass (further items,
-// for windows wider than the workgroup, are loaded where they are used), and
-// the block's lower triangle is loaded into registers and mirrored into LDS.
+// One step of one sweep, executed by the whole workgroup.  The left pass (rows
+// p..p+m of columns k+1 .. p-1) and the right pass over the rows below the
+// block (p+m+1 .. L) touch disjoint entries, so they run at the same time: the
+// first kSymHalf threads take the left pass, thread `lt` the column k+1+lt, and
+// then the block's columns; the others take the rows below the block, thread
+// `rt` the row p+m+1+rt (further items, for windows wider than a group, are
+// loaded where they are used).  Only the block needs both passes in order: its
+// columns after the left pass, then its rows after the right pass, by one
+// thread per row, which stores the row's part of the lower triangle itself.
+// Every global load of the step is issued at its start, the reflector column
+// first (the reflector is formed while the others are in flight); the block's
+// lower triangle is loaded into registers and mirrored into LDS.
 template <typename T, int TWM>
 __device__ __forceinline__ void sym_step(gptr<T> W, int64_t ldw, int n, int b, int k, int p, int m,
-                                         typename Compute<T>::type* blk, double* scr) {
+                                         typename Compute<T>::type* blk, typename Compute<T>::type* stage,
+                                         double* scr) {
     using C = typename Compute<T>::type;
     constexpr int LDB = TWM + 1;
     constexpr int NBE = (LDB * LDB + kSymThreads - 1) / kSymThreads;  // block entries per thread
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
+    const bool left = tid < kSymHalf;
+    const int gt = left ? tid : tid - kSymHalf;  // thread index within its group
     auto at = [&](int i, int q) { return W + ((int64_t)(i - q) + (int64_t)q * ldw); };
     const int nq = p - k - 1;                 // columns k+1 .. p-1 left of the block
     const int L = min(p + m + b, n - 1);
-    const int nrows = L - p + 1;              // rows p .. L of the right pass
+    const int nout = L - p - m;               // rows p+m+1 .. L below the block
     const int64_t rs = ldw - 1;               // stride of a row segment
+    const int rs32 = (int)rs;
     // ---- loads ----
     const double xl = static_cast<double>(*at(p + min(lane, m), k));
-    C aL[TWM + 1], aR[TWM + 1];
-    if (tid < nq) {
-        const gptr<T> col = at(p, k + 1 + tid);
+    C a[TWM + 1];  // the left group's column, or the right group's row
+    if (left && gt < nq) {
+        const gptr<T> col = at(p, k + 1 + gt);
 #pragma unroll
-        for (int t = 0; t <= TWM; ++t) aL[t] = to_c(col[min(t, m)]);
+        for (int t = 0; t <= TWM; ++t) a[t] = to_c(col[min(t, m)]);
     }
-    if (tid > m && tid < nrows) {
-        const gptr<T> row = at(p + tid, p);
+    if (!left && gt < nout) {
+        const gptr<T> row = at(p + m + 1 + gt, p);
 #pragma unroll
-        for (int t = 0; t <= TWM; ++t) aR[t] = to_c(row[(int64_t)min(t, m) * rs]);
+        for (int t = 0; t <= TWM; ++t) a[t] = to_c(row[(int64_t)min(t, m) * rs]);
     }
     C bv[NBE];
 #pragma unroll
@@ -118,65 +131,85 @@ __device__ __forceinline__ void sym_step(gptr<T> W, int64_t ldw, int n, int b, i
         }
     }
     __syncthreads();
-    // ---- left pass: one thread per column ----
-    for (int ci = tid; ci < nq + m + 1; ci += kSymThreads) {
-        if (ci < nq) {
-            const gptr<T> col = at(p, k + 1 + ci);
-            if (ci != tid) {
+    if (left) {
+        // ---- left pass: one thread per column (the columns left of the block, then the block's).
+        // A wave's updated columns go through its LDS staging block and are written back as
+        // contiguous runs (lane -> column u*CPI + lane/TWM, row lane%TWM of store u; row TWM of
+        // every column in one more store), so the stores are coalesced. ----
+        C* wblk = stage + (tid / kWave) * (kWave * LDB);
+        constexpr int CPI = kWave / TWM;
+        const int sub = lane / TWM, tr = lane % TWM;
+        for (int c0 = tid - lane; c0 < nq + m + 1; c0 += kSymHalf) {  // the wave's first column
+            const int ci = c0 + lane;
+            if (ci < nq) {
+                const gptr<T> col = at(p, k + 1 + ci);
+                if (ci != gt) {
 #pragma unroll
-                for (int t = 0; t <= TWM; ++t) aL[t] = to_c(col[min(t, m)]);
+                    for (int t = 0; t <= TWM; ++t) a[t] = to_c(col[min(t, m)]);
+                }
+#pragma unroll
+                for (int t = 0; t <= TWM; ++t) a[t] = t <= m ? a[t] : C(0);
+                if (taud != 0.0) apply_segment<C, TWM>(a, vs, tau, m);
+#pragma unroll
+                for (int t = 0; t <= TWM; ++t) wblk[lane * LDB + t] = a[t];
+            } else if (ci < nq + m + 1) {
+                const int t2 = ci - nq;
+#pragma unroll
+                for (int t = 0; t <= TWM; ++t) a[t] = t <= m ? blk[t + t2 * LDB] : C(0);
+                if (taud != 0.0) apply_segment<C, TWM>(a, vs, tau, m);
+#pragma unroll
+                for (int t = 0; t <= TWM; ++t)
+                    if (t <= m) blk[t + t2 * LDB] = a[t];
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (c0 < nq) {
+                const int cmax = min(nq - c0, kWave);  // columns of this wave left of the block
+                // column c0 + x starts x * rs elements after column c0
+                const Rsrc base = make_rsrc(wave_uniform(at(p, k + 1 + c0)));
+#pragma unroll
+                for (int u = 0; u < TWM; ++u) a[u] = wblk[(u * CPI + sub) * LDB + tr];
+                a[TWM] = wblk[lane * LDB + TWM];
+                const int o = sub * rs32 + tr;
+                // the stride is made opaque so that the per-store offsets are formed at the stores
+                int step = CPI * rs32;
+                asm volatile("" : "+s"(step));
+#pragma unroll
+                for (int u = 0; u < TWM; ++u)
+                    if (tr <= m && u * CPI + sub < cmax) buf_st<T>(base, o, u * step, static_cast<T>(a[u]));
+                if (m == TWM && lane < cmax) buf_st<T>(base, lane * rs32, TWM, static_cast<T>(a[TWM]));
+            }
+            __builtin_amdgcn_wave_barrier();  // the block is rewritten by the next iteration
+        }
+    } else {
+        // ---- right pass below the block: one thread per row ----
+        for (int ri = gt; ri < nout; ri += kSymThreads - kSymHalf) {
+            const gptr<T> row = at(p + m + 1 + ri, p);  // A(p+m+1+ri, p+t) = row[t * rs]
+            if (ri != gt) {
+#pragma unroll
+                for (int t = 0; t <= TWM; ++t) a[t] = to_c(row[(int64_t)min(t, m) * rs]);
             }
 #pragma unroll
-            for (int t = 0; t <= TWM; ++t) aL[t] = t <= m ? aL[t] : C(0);
-            if (taud != 0.0) apply_segment<C, TWM>(aL, vs, tau, m);
+            for (int t = 0; t <= TWM; ++t) a[t] = t <= m ? a[t] : C(0);
+            if (taud != 0.0) apply_segment<C, TWM>(a, vs, tau, m);
 #pragma unroll
             for (int t = 0; t <= TWM; ++t)
-                if (t <= m) st_agent(col + t, static_cast<T>(aL[t]));
-        } else {
-            const int t2 = ci - nq;
-            C av[TWM + 1];
-#pragma unroll
-            for (int t = 0; t <= TWM; ++t) av[t] = t <= m ? blk[t + t2 * LDB] : C(0);
-            if (taud != 0.0) apply_segment<C, TWM>(av, vs, tau, m);
-#pragma unroll
-            for (int t = 0; t <= TWM; ++t)
-                if (t <= m) blk[t + t2 * LDB] = av[t];
+                if (t <= m) st_agent(row + (int64_t)t * rs, static_cast<T>(a[t]));
         }
     }
     __syncthreads();
-    // ---- right pass: one thread per row (the block's rows, then rows p+m+1 .. L) ----
-    for (int ri = tid; ri < nrows; ri += kSymThreads) {
-        if (ri <= m) {
-            C av[TWM + 1];
+    // ---- the block's rows: right pass, then the row's part of the lower triangle goes back ----
+    if (tid <= m) {
+        const int ri = tid;
 #pragma unroll
-            for (int t = 0; t <= TWM; ++t) av[t] = t <= m ? blk[ri + t * LDB] : C(0);
-            if (taud != 0.0) apply_segment<C, TWM>(av, vs, tau, m);
+        for (int t = 0; t <= TWM; ++t) a[t] = t <= m ? blk[ri + t * LDB] : C(0);
+        if (taud != 0.0) apply_segment<C, TWM>(a, vs, tau, m);
 #pragma unroll
-            for (int t = 0; t <= TWM; ++t)
-                if (t <= m) blk[ri + t * LDB] = av[t];
-        } else {
-            const gptr<T> row = at(p + ri, p);  // A(p + ri, p + t) = row[t * rs]
-            if (ri != tid) {
-#pragma unroll
-                for (int t = 0; t <= TWM; ++t) aR[t] = to_c(row[(int64_t)min(t, m) * rs]);
-            }
-#pragma unroll
-            for (int t = 0; t <= TWM; ++t) aR[t] = t <= m ? aR[t] : C(0);
-            if (taud != 0.0) apply_segment<C, TWM>(aR, vs, tau, m);
-#pragma unroll
-            for (int t = 0; t <= TWM; ++t)
-                if (t <= m) st_agent(row + (int64_t)t * rs, static_cast<T>(aR[t]));
-        }
+        for (int t = 0; t <= TWM; ++t)
+            if (t <= ri) st_agent(at(p + ri, p + t), static_cast<T>(a[t]));
     }
-    __syncthreads();
-    // ---- the block's lower triangle goes back; column k becomes (beta, 0, ..., 0) ----
-#pragma unroll
-    for (int z = 0; z < NBE; ++z) {
-        const int e = tid + z * kSymThreads;
-        const int t = e / (m + 1), s = e - t * (m + 1);
-        if (e < (m + 1) * (m + 1) && s >= t) st_agent(at(p + s, p + t), static_cast<T>(blk[s + t * LDB]));
-    }
-    if (tid <= m) st_agent(at(p + tid, k), static_cast<T>(tid == 0 ? betad : 0.0));
+    // column k becomes (beta, 0, ..., 0); every wave read its segment before the barriers above
+    if (tid >= kSymHalf && tid - kSymHalf <= m)
+        st_agent(at(p + tid - kSymHalf, k), static_cast<T>(tid == kSymHalf ? betad : 0.0));
 }
 
 // One stage; progress[r] = steps completed by sweep r, kDone once it and every
@@ -187,6 +220,7 @@ __global__ __launch_bounds__(kSymThreads) void bb_sym_stage(SymStageArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     using Lay = SymLds<C, TWM>;
     C* blk = reinterpret_cast<C*>(smem + Lay::block);
+    C* stg = reinterpret_cast<C*>(smem + Lay::stage);
     double* scr = reinterpret_cast<double*>(smem + Lay::scratch + Lay::scratch_per_wave * (threadIdx.x / kWave));
     __shared__ int s_r, s_ok;
     const gptr<T> W = to_global(reinterpret_cast<T*>(a.W));
@@ -226,7 +260,7 @@ __global__ __launch_bounds__(kSymThreads) void bb_sym_stage(SymStageArgs a) {
                 p = k + b;
                 m = min(tw, n - 1 - p);
             }
-            sym_step<T, TWM>(W, a.ldw, n, b, k, p, m, blk, scr);
+            sym_step<T, TWM>(W, a.ldw, n, b, k, p, m, blk, stg, scr);
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();  // every wave's agent-scope stores are complete
             if (threadIdx.x == 0)
