@@ -18,7 +18,8 @@
 // order); step j of sweep r waits until sweep r-1 has completed j + H steps or is
 // done, with H = 2 for c >= 2 and 3 for c = 1 (the smallest lag for which steps
 // left unordered touch disjoint entries; checked exhaustively on the CPU).  So
-// the result equals the sequential order bit for bit.
+// the result equals the sequential order bit for bit.  The entries that are
+// already final one step earlier are loaded before that wait completes.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -78,10 +79,10 @@ __global__ void bb_sym_extract(const T* __restrict__ W, int64_t n, int64_t ldw, 
 // Every global load of the step is issued at its start, the reflector column
 // first (the reflector is formed while the others are in flight); the block's
 // lower triangle is loaded into registers and mirrored into LDS.
-template <typename T, int TWM>
-__device__ __forceinline__ void sym_step(gptr<T> W, int64_t ldw, int n, int b, int k, int p, int m,
+template <typename T, int TWM, typename WaitFull>
+__device__ __forceinline__ void sym_step(gptr<T> W, int64_t ldw, int n, int b, int k, int p, int m, int early_end,
                                          typename Compute<T>::type* blk, typename Compute<T>::type* stage,
-                                         double* scr) {
+                                         double* scr, WaitFull&& wait_full) {
     using C = typename Compute<T>::type;
     constexpr int LDB = TWM + 1;
     constexpr int NBE = (LDB * LDB + kSymThreads - 1) / kSymThreads;  // block entries per thread
@@ -103,7 +104,9 @@ __device__ __forceinline__ void sym_step(gptr<T> W, int64_t ldw, int n, int b, i
 #pragma unroll
         for (int t = 0; t <= TWM; ++t) a[t] = to_c(col[min(t, m)]);
     }
-    if (!left && gt < nout) {
+    // rows below the block with p + m + 1 + gt < p + early_end are final before the full wait
+    const bool row_early = !left && gt < nout && m + 1 + gt < early_end;
+    if (row_early) {
         const gptr<T> row = at(p + m + 1 + gt, p);
 #pragma unroll
         for (int t = 0; t <= TWM; ++t) a[t] = to_c(row[(int64_t)min(t, m) * rs]);
@@ -130,7 +133,9 @@ __device__ __forceinline__ void sym_step(gptr<T> W, int64_t ldw, int n, int b, i
             blk[t + s * LDB] = bv[z];
         }
     }
-    __syncthreads();
+    // the full dependency; it ends with a workgroup barrier, after which the rest is
+    // loaded and every store is made
+    if (!wait_full()) return;
     if (left) {
         // ---- left pass: one thread per column (the columns left of the block, then the block's).
         // A wave's updated columns go through its LDS staging block and are written back as
@@ -184,7 +189,7 @@ __device__ __forceinline__ void sym_step(gptr<T> W, int64_t ldw, int n, int b, i
         // ---- right pass below the block: one thread per row ----
         for (int ri = gt; ri < nout; ri += kSymThreads - kSymHalf) {
             const gptr<T> row = at(p + m + 1 + ri, p);  // A(p+m+1+ri, p+t) = row[t * rs]
-            if (ri != gt) {
+            if (ri != gt || !row_early) {
 #pragma unroll
                 for (int t = 0; t <= TWM; ++t) a[t] = to_c(row[(int64_t)min(t, m) * rs]);
             }
@@ -239,9 +244,16 @@ __global__ __launch_bounds__(kSymThreads) void bb_sym_stage(SymStageArgs a) {
         const int len = steps_of(r);
         const int len_prev = r > 0 ? steps_of(r - 1) : 0;
         int known = 0;
+        // Two-part wait.  Once sweep r-1 has completed one step less than the rule
+        // asks, column k, the columns left of the block, the block and the rows
+        // below it up to p + early_end - 1 are final (an exhaustive check of the
+        // schedule shows it for every stage shape): they are loaded and the
+        // reflector is formed first; the rest is loaded, and everything is stored,
+        // after the full wait.
+        const int early_end = c == 1 ? 2 * b - 1 : b - 1;
         for (int j = 0; j < len; ++j) {
             if (threadIdx.x == 0 && r > 0) {
-                const int need = j + H > len_prev ? kDone : j + H;
+                const int need = j + H - 1 > len_prev ? kDone : j + H - 1;
                 if (need > known) {
                     const int v = poll_ge(a.progress + (r - 1), need, a.abort_flag, a.err_word, a.spin_limit);
                     if (v < 0) s_ok = 0;
@@ -250,6 +262,18 @@ __global__ __launch_bounds__(kSymThreads) void bb_sym_stage(SymStageArgs a) {
             }
             __syncthreads();
             if (!s_ok) return;
+            auto wait_full = [&]() -> bool {  // every thread of the workgroup
+                if (threadIdx.x == 0 && r > 0 && s_ok) {
+                    const int need = j + H > len_prev ? kDone : j + H;
+                    if (need > known) {
+                        const int v = poll_ge(a.progress + (r - 1), need, a.abort_flag, a.err_word, a.spin_limit);
+                        if (v < 0) s_ok = 0;
+                        else known = v;
+                    }
+                }
+                __syncthreads();
+                return s_ok != 0;
+            };
             int k, p, m;
             if (j == 0) {
                 k = r;
@@ -260,7 +284,8 @@ __global__ __launch_bounds__(kSymThreads) void bb_sym_stage(SymStageArgs a) {
                 p = k + b;
                 m = min(tw, n - 1 - p);
             }
-            sym_step<T, TWM>(W, a.ldw, n, b, k, p, m, blk, stg, scr);
+            sym_step<T, TWM>(W, a.ldw, n, b, k, p, m, early_end, blk, stg, scr, wait_full);
+            if (!s_ok) return;
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();  // every wave's agent-scope stores are complete
             if (threadIdx.x == 0)
