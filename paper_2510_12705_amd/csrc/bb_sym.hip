@@ -133,30 +133,44 @@ __device__ __forceinline__ void sym_step(gptr<T> W, int64_t ldw, int n, int b, i
             blk[t + s * LDB] = bv[z];
         }
     }
+    // A left-group wave's updated columns go through its LDS staging block and are
+    // written back as contiguous runs (lane -> column u*CPI + lane/TWM, row lane%TWM
+    // of store u; row TWM of every column in one more store), so the stores are
+    // coalesced.
+    C* wblk = stage + (tid / kWave) * (kWave * LDB);
+    // A thread's first column or row, when loaded before the full wait, is also
+    // updated before it (into the staging block, or kept in registers); only the
+    // stores wait.
+    const bool pre_left = left && gt < nq;
+    if (pre_left || row_early) {
+#pragma unroll
+        for (int t = 0; t <= TWM; ++t) a[t] = t <= m ? a[t] : C(0);
+        if (taud != 0.0) apply_segment<C, TWM>(a, vs, tau, m);
+        if (pre_left) {
+#pragma unroll
+            for (int t = 0; t <= TWM; ++t) wblk[lane * LDB + t] = a[t];
+        }
+    }
     // the full dependency; it ends with a workgroup barrier, after which the rest is
     // loaded and every store is made
     if (!wait_full()) return;
     if (left) {
-        // ---- left pass: one thread per column (the columns left of the block, then the block's).
-        // A wave's updated columns go through its LDS staging block and are written back as
-        // contiguous runs (lane -> column u*CPI + lane/TWM, row lane%TWM of store u; row TWM of
-        // every column in one more store), so the stores are coalesced. ----
-        C* wblk = stage + (tid / kWave) * (kWave * LDB);
+        // ---- left pass: one thread per column (the columns left of the block, then the block's) ----
         constexpr int CPI = kWave / TWM;
         const int sub = lane / TWM, tr = lane % TWM;
         for (int c0 = tid - lane; c0 < nq + m + 1; c0 += kSymHalf) {  // the wave's first column
             const int ci = c0 + lane;
             if (ci < nq) {
-                const gptr<T> col = at(p, k + 1 + ci);
-                if (ci != gt) {
+                if (ci != gt) {  // (the first column is in the staging block already)
+                    const gptr<T> col = at(p, k + 1 + ci);
 #pragma unroll
                     for (int t = 0; t <= TWM; ++t) a[t] = to_c(col[min(t, m)]);
+#pragma unroll
+                    for (int t = 0; t <= TWM; ++t) a[t] = t <= m ? a[t] : C(0);
+                    if (taud != 0.0) apply_segment<C, TWM>(a, vs, tau, m);
+#pragma unroll
+                    for (int t = 0; t <= TWM; ++t) wblk[lane * LDB + t] = a[t];
                 }
-#pragma unroll
-                for (int t = 0; t <= TWM; ++t) a[t] = t <= m ? a[t] : C(0);
-                if (taud != 0.0) apply_segment<C, TWM>(a, vs, tau, m);
-#pragma unroll
-                for (int t = 0; t <= TWM; ++t) wblk[lane * LDB + t] = a[t];
             } else if (ci < nq + m + 1) {
                 const int t2 = ci - nq;
 #pragma unroll
@@ -189,13 +203,13 @@ __device__ __forceinline__ void sym_step(gptr<T> W, int64_t ldw, int n, int b, i
         // ---- right pass below the block: one thread per row ----
         for (int ri = gt; ri < nout; ri += kSymThreads - kSymHalf) {
             const gptr<T> row = at(p + m + 1 + ri, p);  // A(p+m+1+ri, p+t) = row[t * rs]
-            if (ri != gt || !row_early) {
+            if (ri != gt || !row_early) {  // (an early first row is updated already)
 #pragma unroll
                 for (int t = 0; t <= TWM; ++t) a[t] = to_c(row[(int64_t)min(t, m) * rs]);
-            }
 #pragma unroll
-            for (int t = 0; t <= TWM; ++t) a[t] = t <= m ? a[t] : C(0);
-            if (taud != 0.0) apply_segment<C, TWM>(a, vs, tau, m);
+                for (int t = 0; t <= TWM; ++t) a[t] = t <= m ? a[t] : C(0);
+                if (taud != 0.0) apply_segment<C, TWM>(a, vs, tau, m);
+            }
 #pragma unroll
             for (int t = 0; t <= TWM; ++t)
                 if (t <= m) st_agent(row + (int64_t)t * rs, static_cast<T>(a[t]));
