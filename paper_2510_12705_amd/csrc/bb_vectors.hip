@@ -52,31 +52,33 @@ __global__ void bb_identity(double* __restrict__ X, int64_t n, int64_t ldx) {
 }
 
 // blockIdx.y = 0: V from the right reflectors, 1: U from the left reflectors.
-// One wave per workgroup.  The ring holds R = W + ahead columns: the column that
-// enters at sweep r is loaded `ahead` reflectors before its first use, so its
-// latency hides behind that many dot products.  The reflectors of one pass over
-// the ring (R consecutive sweeps of one step: R * wlog contiguous log entries)
-// sit in one of two LDS buffers; while a pass runs, the next pass's entries are
-// loaded in chunks of kChunk reflectors (coalesced, each chunk issued at the
-// start of the matching chunk of this pass and written to the other buffer at
-// its end), so few registers hold them and their latency is hidden.
+// One wave per workgroup.  For the current reflector (sweep r, support
+// p .. p+W-1, p = p0 + r) the thread holds the row's columns p .. p+R-1,
+// R = W + ahead: the column that enters at sweep r is loaded `ahead` reflectors
+// before its first use, so its latency hides behind that many dot products.
+// Reflectors are processed in blocks of kBlk: within a block the register
+// holding a column is fixed (reflector u of the block uses x[u .. u+W-1], and
+// the column entering behind it goes to x[u+R]), so every index is a
+// compile-time constant; after the block the registers move down by kBlk.  The
+// reflectors of a block (kBlk consecutive sweeps of one step: kBlk * wlog
+// contiguous log entries) sit in one of two LDS buffers; the next block's are
+// loaded (coalesced) at the start of a block and written to the other buffer at
+// its end.  Keeping the unrolled body to one block keeps the kernel's code well
+// inside the instruction cache.
 template <int TWM>
 constexpr int ring_ahead() { return TWM >= 64 ? 8 : 16; }
-template <int TWM>
-constexpr int ring_size() { return TWM + 1 + ring_ahead<TWM>(); }
-constexpr int kChunk = 16;
+constexpr int kBlk = 8;
 
 template <int TWM>
 __global__ __launch_bounds__(64) void bb_backtransform(double* __restrict__ Xv, int64_t ldv, double* __restrict__ Xu,
                                                        int64_t ldu, int n, int b, int c, int nsweeps, int nsteps,
                                                        const double* __restrict__ log, int wlog) {
     constexpr int W = TWM + 1;
-    constexpr int R = ring_size<TWM>();
-    constexpr int PASS = R * W;                                 // LDS entries of one pass (wlog <= W)
-    constexpr int CE = kChunk * W;                              // entries of one chunk
-    constexpr int Q = (CE + kWaveLanes - 1) / kWaveLanes;       // chunk entries per lane
-    constexpr int NCH = (R + kChunk - 1) / kChunk;              // chunks per pass
-    extern __shared__ double vbuf[];                            // [2][R][W]
+    constexpr int R = W + ring_ahead<TWM>();
+    constexpr int U = kBlk;
+    constexpr int BE = U * W;                             // LDS entries of one block (wlog <= W)
+    constexpr int Q = (BE + kWaveLanes - 1) / kWaveLanes;  // block entries per lane
+    extern __shared__ double vbuf[];                       // [2][U][W]
     double* __restrict__ X = blockIdx.y == 0 ? Xv : Xu;
     const int64_t ldx = blockIdx.y == 0 ? ldv : ldu;
     if (!X) return;
@@ -87,24 +89,21 @@ __global__ __launch_bounds__(64) void bb_backtransform(double* __restrict__ Xv, 
     const bool row = i < n;  // lanes past the last row compute on zeros and store nothing
     gptr_v<double> xi = (gptr_v<double>)(X + (row ? i : 0));
     auto ld = [&](int col) -> double { return (row && col < n) ? xi[(int64_t)col * ldx] : 0.0; };
-    // chunk k of the pass starting at sweep r0: entries of sweeps r0 + k*kChunk + u'
-    // (u' < kChunk, within the pass) as [u][t], zero beyond wlog or rcount
-    auto fetch = [&](const double* __restrict__ slots, int r0, int k, int rcount, double (&q)[Q]) {
+    // the block of sweeps r0 .. r0+U-1: entries [u][t], zero beyond wlog or rcount
+    auto fetch = [&](const double* __restrict__ slots, int r0, int rcount, double (&q)[Q]) {
 #pragma unroll
         for (int z = 0; z < Q; ++z) {
-            const int e = lane + kWaveLanes * z;  // entry of the chunk: u' * W + t
-            const int up = e / W, t = e - up * W;
-            const int u = k * kChunk + up;        // reflector of the pass
+            const int e = lane + kWaveLanes * z;  // entry of the block: u * W + t
+            const int u = e / W, t = e - u * W;
             const int r = r0 + u;
-            q[z] = (e < CE && u < R && t < wlog && r < rcount) ? slots[(int64_t)r * wlog + t] : 0.0;
+            q[z] = (e < BE && t < wlog && r < rcount) ? slots[(int64_t)r * wlog + t] : 0.0;
         }
     };
-    auto stage = [&](int buf, int k, const double (&q)[Q]) {
+    auto stage = [&](int buf, const double (&q)[Q]) {
 #pragma unroll
         for (int z = 0; z < Q; ++z) {
             const int e = lane + kWaveLanes * z;
-            const int u = k * kChunk + e / W;
-            if (e < CE && u < R) vbuf[buf * PASS + k * CE + e] = q[z];
+            if (e < BE) vbuf[buf * BE + e] = q[z];
         }
         __builtin_amdgcn_wave_barrier();
     };
@@ -112,52 +111,54 @@ __global__ __launch_bounds__(64) void bb_backtransform(double* __restrict__ Xv, 
         const int rcount = min(n - 1 - c - j * b, nsweeps);  // sweeps with p = r + c + j b <= n - 2
         if (rcount <= 0) continue;
         const int p0 = c + j * b;
-        double x[R];  // slot s holds column p0 + s + R k during the k-th pass over the ring
+        double x[R + U];  // at the start of the block at sweep rb: x[s] = column p0 + rb + s (s < R)
 #pragma unroll
         for (int t = 0; t < R; ++t) x[t] = ld(p0 + t);
         const double* __restrict__ slots = lg + (int64_t)j * nsweeps * wlog;
         double q[Q];
-        __builtin_amdgcn_wave_barrier();  // the previous step's last pass has read its buffer
-        for (int k = 0; k < NCH; ++k) {
-            fetch(slots, 0, k, rcount, q);
-            stage(0, k, q);
-        }
+        __builtin_amdgcn_wave_barrier();  // the previous step's last block has read its buffer
+        fetch(slots, 0, rcount, q);
+        stage(0, q);
         int buf = 0;
-        for (int rb = 0; rb < rcount; rb += R) {
-            const double* vb = vbuf + buf * PASS;
-#pragma clang loop unroll(full)
-            for (int u = 0; u < R; ++u) {
-                if (u % kChunk == 0) fetch(slots, rb + R, u / kChunk, rcount, q);  // next pass, this chunk
+        for (int rb = 0;; rb += U) {
+            fetch(slots, rb + U, rcount, q);  // the next block's reflectors
+            const double* vb = vbuf + buf * BE;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
                 const int r = rb + u;
                 if (r < rcount) {
                     const double* sl = vb + u * W;
                     const double tau = sl[0];
                     if (tau != 0.0) {
-                        // support p .. p + W - 1 (p = p0 + r) sits in slots u, u+1, ... (mod R)
                         double w = 0.0;
                         w = w + x[u] * 1.0;
-#pragma clang loop unroll(full)
-                        for (int t = 1; t < W; ++t) w = w + x[(u + t) % R] * sl[t];
+#pragma unroll
+                        for (int t = 1; t < W; ++t) w = w + x[u + t] * sl[t];
                         const double tw = tau * w;
                         x[u] = x[u] - tw * 1.0;
-#pragma clang loop unroll(full)
-                        for (int t = 1; t < W; ++t) x[(u + t) % R] = x[(u + t) % R] - tw * sl[t];
+#pragma unroll
+                        for (int t = 1; t < W; ++t) x[u + t] = x[u + t] - tw * sl[t];
                     }
-                    // column p leaves the window for good in this step; column p + R enters its slot
+                    // column p leaves the window for good in this step; column p + R enters
                     const int p = p0 + r;
                     if (row) xi[(int64_t)p * ldx] = x[u];
-                    x[u] = ld(p + R);
+                    x[u + R] = ld(p + R);
                 }
-                if (u % kChunk == kChunk - 1 || u == R - 1) stage(buf ^ 1, u / kChunk, q);
             }
-            buf ^= 1;
-        }
-        // slot s holds column p0 + s + R * (number of sweeps r < rcount with r = s mod R)
+            if (rb + U >= rcount) {
+                // the window's columns p0 + rcount .. + R - 1 sit in x[rcount - rb ..]
+                const int done = rcount - rb;
 #pragma unroll
-        for (int s = 0; s < R; ++s) {
-            const int passes = rcount > s ? (rcount - s + R - 1) / R : 0;
-            const int col = p0 + s + R * passes;
-            if (row && col < n) xi[(int64_t)col * ldx] = x[s];
+                for (int s = 0; s < R + U; ++s) {
+                    const int col = p0 + rb + s;
+                    if (s >= done && s < done + R && row && col < n) xi[(int64_t)col * ldx] = x[s];
+                }
+                break;
+            }
+            stage(buf ^ 1, q);
+            buf ^= 1;
+#pragma unroll
+            for (int t = 0; t < R; ++t) x[t] = x[t + U];
         }
     }
 }
@@ -172,7 +173,7 @@ hipError_t launch_identity(double* X, int64_t n, int64_t ldx, hipStream_t st) {
 template <int TWM>
 static void launch_bt(dim3 grid, hipStream_t st, double* Xv, int64_t ldv, double* Xu, int64_t ldu, int n, int b, int c,
                       int nsweeps, int nsteps, const double* log, int wlog) {
-    const size_t lds = sizeof(double) * 2 * (size_t)ring_size<TWM>() * (TWM + 1);
+    const size_t lds = sizeof(double) * 2 * (size_t)kBlk * (TWM + 1);
     hipLaunchKernelGGL(bb_backtransform<TWM>, grid, dim3(kWaveLanes), lds, st, Xv, ldv, Xu, ldu, n, b, c, nsweeps,
                        nsteps, log, wlog);
 }
