@@ -747,8 +747,8 @@ int bb_sym_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, int6
     int* counters = reinterpret_cast<int*>(W + band_bytes);
     rc = check_hip(bbk::launch_fill(counters, per_stage * std::max(nstages, 1), 0, st));
     if (!rc) rc = check_hip(bbk::launch_sym_pack(dtype, band, ldband, n, bb, W, ldw, st));
-    // one 512-thread workgroup fits a CU (the FP64 32-wide step uses 240 registers per lane)
-    const int gpc = prm.groups_per_cu ? prm.groups_per_cu : 1;
+    // workgroups per CU: as many as fit (a 512-thread workgroup of the FP64 32-wide step
+    // uses 234 registers per lane, so one; two of 256 threads)
     if (bb > 1) {
         int s = 0;
         for (bbp::Stage sg = bbp::stage_first(bb, tw); !rc; sg = bbp::stage_next(sg, tw), ++s) {
@@ -767,8 +767,10 @@ int bb_sym_reduce(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, int6
             a.err_word = ds->err_dev;
             a.spin_limit = spin_limit();
             if (a.nsweeps > 0) {
+                const int nt = bbk::sym_stage_threads(sg.b, sg.tw);
+                const int gpc = prm.groups_per_cu ? prm.groups_per_cu : (nt == 256 ? 2 : 1);
                 const int grid = (int)std::min<int64_t>(a.nsweeps, (int64_t)ds->cus * gpc);
-                rc = check_hip(bbk::launch_sym_stage(dtype, a, bbp::kernel_twm(sg.tw), grid, st));
+                rc = check_hip(bbk::launch_sym_stage(dtype, a, bbp::kernel_twm(sg.tw), nt, grid, st));
             }
             if (sg.c <= 1) break;
         }

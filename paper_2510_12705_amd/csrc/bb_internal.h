@@ -42,7 +42,9 @@ struct SymStageArgs {
     int* err_word;
     unsigned spin_limit;
 };
-hipError_t launch_sym_stage(int dtype, const SymStageArgs& a, int twm, int grid, hipStream_t st);
+// threads per workgroup of the symmetric stage kernel for a stage (b, tw): 256 or 512
+int sym_stage_threads(int b, int tw);
+hipError_t launch_sym_stage(int dtype, const SymStageArgs& a, int twm, int nt, int grid, hipStream_t st);
 hipError_t launch_sym_pack(int dtype, const void* band, int64_t ldband, int64_t n, int64_t b, void* W, int64_t ldw,
                            hipStream_t st);
 hipError_t launch_sym_extract(int dtype, const void* W, int64_t n, int64_t ldw, double* d, double* e, hipStream_t st);

@@ -31,20 +31,22 @@
 
 namespace bbk {
 
-constexpr int kSymThreads = 512;
-constexpr int kSymHalf = kSymThreads / 2;  // threads of the left group (the right group: the rest)
+// Threads per workgroup NT: 512, or 256 for stages whose left pass and rows
+// below the block fit 128 threads each (b + TW <= 128), so that two sweeps fit
+// a CU where the pipeline needs many sweeps in flight.  The first NT / 2
+// threads form the left group, the others the right group.
 
 // LDS of one workgroup: the (TWM+1)^2 block (full square, compute type), one
 // staging block of kWave columns of TWM+1 entries per wave of the left group,
 // and a reflector scratch of 2 (TWM+1) doubles per wave.
-template <typename C, int TWM>
+template <typename C, int TWM, int NT>
 struct SymLds {
     static constexpr int LDB = TWM + 1;
     static constexpr size_t block = 0;
     static constexpr size_t stage = (sizeof(C) * LDB * LDB + 15) / 16 * 16;
-    static constexpr size_t scratch = stage + sizeof(C) * kSymHalf * LDB;
+    static constexpr size_t scratch = stage + sizeof(C) * (NT / 2) * LDB;
     static constexpr size_t scratch_per_wave = sizeof(double) * 2 * LDB;
-    static constexpr size_t bytes = scratch + scratch_per_wave * (kSymThreads / kWave);
+    static constexpr size_t bytes = scratch + scratch_per_wave * (NT / kWave);
 };
 
 template <typename T>
@@ -70,7 +72,7 @@ __global__ void bb_sym_extract(const T* __restrict__ W, int64_t n, int64_t ldw, 
 // One step of one sweep, executed by the whole workgroup.  The left pass (rows
 // p..p+m of columns k+1 .. p-1) and the right pass over the rows below the
 // block (p+m+1 .. L) touch disjoint entries, so they run at the same time: the
-// first kSymHalf threads take the left pass, thread `lt` the column k+1+lt, and
+// first NT / 2 threads take the left pass, thread `lt` the column k+1+lt, and
 // then the block's columns; the others take the rows below the block, thread
 // `rt` the row p+m+1+rt (further items, for windows wider than a group, are
 // loaded where they are used).  Only the block needs both passes in order: its
@@ -79,12 +81,14 @@ __global__ void bb_sym_extract(const T* __restrict__ W, int64_t n, int64_t ldw, 
 // Every global load of the step is issued at its start, the reflector column
 // first (the reflector is formed while the others are in flight); the block's
 // lower triangle is loaded into registers and mirrored into LDS.
-template <typename T, int TWM, typename WaitFull>
+template <typename T, int TWM, int NT, typename WaitFull>
 __device__ __forceinline__ void sym_step(gptr<T> W, int64_t ldw, int n, int b, int k, int p, int m, int early_end,
                                          typename Compute<T>::type* blk, typename Compute<T>::type* stage,
                                          double* scr, WaitFull&& wait_full) {
     using C = typename Compute<T>::type;
     constexpr int LDB = TWM + 1;
+    constexpr int kSymThreads = NT;
+    constexpr int kSymHalf = NT / 2;
     constexpr int NBE = (LDB * LDB + kSymThreads - 1) / kSymThreads;  // block entries per thread
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
@@ -233,11 +237,11 @@ __device__ __forceinline__ void sym_step(gptr<T> W, int64_t ldw, int n, int b, i
 
 // One stage; progress[r] = steps completed by sweep r, kDone once it and every
 // earlier sweep finished.
-template <typename T, int TWM>
-__global__ __launch_bounds__(kSymThreads) void bb_sym_stage(SymStageArgs a) {
+template <typename T, int TWM, int NT>
+__global__ __launch_bounds__(NT, NT == 256 ? 2 : 1) void bb_sym_stage(SymStageArgs a) {
     using C = typename Compute<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
-    using Lay = SymLds<C, TWM>;
+    using Lay = SymLds<C, TWM, NT>;
     C* blk = reinterpret_cast<C*>(smem + Lay::block);
     C* stg = reinterpret_cast<C*>(smem + Lay::stage);
     double* scr = reinterpret_cast<double*>(smem + Lay::scratch + Lay::scratch_per_wave * (threadIdx.x / kWave));
@@ -298,7 +302,7 @@ __global__ __launch_bounds__(kSymThreads) void bb_sym_stage(SymStageArgs a) {
                 p = k + b;
                 m = min(tw, n - 1 - p);
             }
-            sym_step<T, TWM>(W, a.ldw, n, b, k, p, m, early_end, blk, stg, scr, wait_full);
+            sym_step<T, TWM, NT>(W, a.ldw, n, b, k, p, m, early_end, blk, stg, scr, wait_full);
             if (!s_ok) return;
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();  // every wave's agent-scope stores are complete
@@ -318,26 +322,34 @@ __global__ __launch_bounds__(kSymThreads) void bb_sym_stage(SymStageArgs a) {
     }
 }
 
-template <typename T, int TWM>
+template <typename T, int TWM, int NT>
 static void launch_sym_twm(const SymStageArgs& a, int grid, hipStream_t st) {
     using C = typename Compute<T>::type;
-    const size_t smem = SymLds<C, TWM>::bytes;
-    hipLaunchKernelGGL((bb_sym_stage<T, TWM>), dim3(grid), dim3(kSymThreads), smem, st, a);
+    const size_t smem = SymLds<C, TWM, NT>::bytes;
+    hipLaunchKernelGGL((bb_sym_stage<T, TWM, NT>), dim3(grid), dim3(NT), smem, st, a);
+}
+
+template <typename T, int TWM>
+static void launch_sym_nt(const SymStageArgs& a, int nt, int grid, hipStream_t st) {
+    if (nt == 256) launch_sym_twm<T, TWM, 256>(a, grid, st);
+    else launch_sym_twm<T, TWM, 512>(a, grid, st);
 }
 
 template <typename T>
-static hipError_t launch_sym_stage_t(const SymStageArgs& a, int twm, int grid, hipStream_t st) {
+static hipError_t launch_sym_stage_t(const SymStageArgs& a, int twm, int nt, int grid, hipStream_t st) {
     switch (twm) {
-        case 8: launch_sym_twm<T, 8>(a, grid, st); break;
-        case 16: launch_sym_twm<T, 16>(a, grid, st); break;
-        case 32: launch_sym_twm<T, 32>(a, grid, st); break;
+        case 8: launch_sym_nt<T, 8>(a, nt, grid, st); break;
+        case 16: launch_sym_nt<T, 16>(a, nt, grid, st); break;
+        case 32: launch_sym_nt<T, 32>(a, nt, grid, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_sym_stage(int dtype, const SymStageArgs& a, int twm, int grid, hipStream_t st) {
-    return dtype == 0 ? launch_sym_stage_t<double>(a, twm, grid, st) : launch_sym_stage_t<float>(a, twm, grid, st);
+int sym_stage_threads(int b, int tw) { return b + tw <= 128 ? 256 : 512; }
+
+hipError_t launch_sym_stage(int dtype, const SymStageArgs& a, int twm, int nt, int grid, hipStream_t st) {
+    return dtype == 0 ? launch_sym_stage_t<double>(a, twm, nt, grid, st) : launch_sym_stage_t<float>(a, twm, nt, grid, st);
 }
 
 hipError_t launch_sym_pack(int dtype, const void* band, int64_t ldband, int64_t n, int64_t b, void* W, int64_t ldw,
