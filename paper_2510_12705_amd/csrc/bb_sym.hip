@@ -31,10 +31,9 @@
 
 namespace bbk {
 
-// Threads per workgroup NT: 512, or 256 for stages whose left pass and rows
-// below the block fit 128 threads each (b + TW <= 128), so that two sweeps fit
-// a CU where the pipeline needs many sweeps in flight.  The first NT / 2
-// threads form the left group, the others the right group.
+// Threads per workgroup NT: 512, or 256 for stages with b <= 64 (the left pass
+// then fits 128 threads and the rows below the block 64), so that two sweeps
+// fit a CU where the pipeline needs many sweeps in flight.
 
 // LDS of one workgroup: the (TWM+1)^2 block (full square, compute type), one
 // staging block of kWave columns of TWM+1 entries per wave of the left group,
@@ -44,7 +43,7 @@ struct SymLds {
     static constexpr int LDB = TWM + 1;
     static constexpr size_t block = 0;
     static constexpr size_t stage = (sizeof(C) * LDB * LDB + 15) / 16 * 16;
-    static constexpr size_t scratch = stage + sizeof(C) * (NT / 2) * LDB;
+    static constexpr size_t scratch = stage + sizeof(C) * (NT == 512 ? 256 : 128) * LDB;
     static constexpr size_t scratch_per_wave = sizeof(double) * 2 * LDB;
     static constexpr size_t bytes = scratch + scratch_per_wave * (NT / kWave);
 };
@@ -69,31 +68,41 @@ __global__ void bb_sym_extract(const T* __restrict__ W, int64_t n, int64_t ldw, 
     }
 }
 
-// One step of one sweep, executed by the whole workgroup.  The left pass (rows
-// p..p+m of columns k+1 .. p-1) and the right pass over the rows below the
-// block (p+m+1 .. L) touch disjoint entries, so they run at the same time: the
-// first NT / 2 threads take the left pass, thread `lt` the column k+1+lt, and
-// then the block's columns; the others take the rows below the block, thread
-// `rt` the row p+m+1+rt (further items, for windows wider than a group, are
-// loaded where they are used).  Only the block needs both passes in order: its
-// columns after the left pass, then its rows after the right pass, by one
-// thread per row, which stores the row's part of the lower triangle itself.
-// Every global load of the step is issued at its start, the reflector column
-// first (the reflector is formed while the others are in flight); the block's
-// lower triangle is loaded into registers and mirrored into LDS.
+// One step of one sweep, executed by the whole workgroup.  Three parts touch
+// disjoint entries and run at the same time in different waves: the left pass
+// over the columns k+1 .. p-1 (rows p..p+m), the right pass over the rows below
+// the block (p+m+1 .. L, columns p..p+m), and the block itself.  The left group
+// (the first SymShape::kLeft threads) takes one column per thread, the right
+// group (the following kRight threads) one row per thread (further items, for
+// windows wider than a group, are loaded where they are used), and the last
+// wave the block: its lanes 0..m apply the left pass to the block's columns,
+// then, after a wave barrier, the right pass to its rows, each lane storing its
+// row's part of the lower triangle.  Every global load of the step is issued at
+// its start, the reflector column first (the reflector is formed while the
+// others are in flight); the block's lower triangle is loaded by all threads
+// and mirrored into LDS.
+template <int NT>
+struct SymShape {
+    static constexpr int kLeft = NT == 512 ? 256 : 128;  // waves 0 .. kLeft/64 - 1
+    static constexpr int kRight = NT - kLeft - kWave;    // then the right group
+    static constexpr int kBlockWave = NT / kWave - 1;    // the last wave
+};
+
 template <typename T, int TWM, int NT, typename WaitFull>
 __device__ __forceinline__ void sym_step(gptr<T> W, int64_t ldw, int n, int b, int k, int p, int m, int early_end,
                                          typename Compute<T>::type* blk, typename Compute<T>::type* stage,
                                          double* scr, WaitFull&& wait_full) {
     using C = typename Compute<T>::type;
+    using Sh = SymShape<NT>;
     constexpr int LDB = TWM + 1;
-    constexpr int kSymThreads = NT;
-    constexpr int kSymHalf = NT / 2;
-    constexpr int NBE = (LDB * LDB + kSymThreads - 1) / kSymThreads;  // block entries per thread
+    constexpr int NBE = (LDB * LDB + NT - 1) / NT;  // block entries per thread
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
-    const bool left = tid < kSymHalf;
-    const int gt = left ? tid : tid - kSymHalf;  // thread index within its group
+    const int wave = tid / kWave;
+    const bool left = tid < Sh::kLeft;
+    const bool blockw = wave == Sh::kBlockWave;
+    const bool right = !left && !blockw;
+    const int gt = left ? tid : tid - Sh::kLeft;  // thread index within its group
     auto at = [&](int i, int q) { return W + ((int64_t)(i - q) + (int64_t)q * ldw); };
     const int nq = p - k - 1;                 // columns k+1 .. p-1 left of the block
     const int L = min(p + m + b, n - 1);
@@ -102,14 +111,14 @@ __device__ __forceinline__ void sym_step(gptr<T> W, int64_t ldw, int n, int b, i
     const int rs32 = (int)rs;
     // ---- loads ----
     const double xl = static_cast<double>(*at(p + min(lane, m), k));
-    C a[TWM + 1];  // the left group's column, or the right group's row
+    C a[TWM + 1];  // the left group's column, the right group's row, the block wave's column / row
     if (left && gt < nq) {
         const gptr<T> col = at(p, k + 1 + gt);
 #pragma unroll
         for (int t = 0; t <= TWM; ++t) a[t] = to_c(col[min(t, m)]);
     }
     // rows below the block with p + m + 1 + gt < p + early_end are final before the full wait
-    const bool row_early = !left && gt < nout && m + 1 + gt < early_end;
+    const bool row_early = right && gt < nout && m + 1 + gt < early_end;
     if (row_early) {
         const gptr<T> row = at(p + m + 1 + gt, p);
 #pragma unroll
@@ -118,7 +127,7 @@ __device__ __forceinline__ void sym_step(gptr<T> W, int64_t ldw, int n, int b, i
     C bv[NBE];
 #pragma unroll
     for (int z = 0; z < NBE; ++z) {
-        const int e = tid + z * kSymThreads;
+        const int e = tid + z * NT;
         const int t = e / (m + 1), s = e - t * (m + 1);
         bv[z] = (e < (m + 1) * (m + 1) && s >= t) ? to_c(*at(p + s, p + t)) : C(0);
     }
@@ -130,7 +139,7 @@ __device__ __forceinline__ void sym_step(gptr<T> W, int64_t ldw, int n, int b, i
     // ---- the block, mirrored to a full square: blk[s + t * LDB] = A(p+s, p+t) ----
 #pragma unroll
     for (int z = 0; z < NBE; ++z) {
-        const int e = tid + z * kSymThreads;
+        const int e = tid + z * NT;
         const int t = e / (m + 1), s = e - t * (m + 1);
         if (e < (m + 1) * (m + 1) && s >= t) {
             blk[s + t * LDB] = bv[z];
@@ -141,7 +150,7 @@ __device__ __forceinline__ void sym_step(gptr<T> W, int64_t ldw, int n, int b, i
     // written back as contiguous runs (lane -> column u*CPI + lane/TWM, row lane%TWM
     // of store u; row TWM of every column in one more store), so the stores are
     // coalesced.
-    C* wblk = stage + (tid / kWave) * (kWave * LDB);
+    C* wblk = stage + wave * (kWave * LDB);
     // A thread's first column or row, when loaded before the full wait, is also
     // updated before it (into the staging block, or kept in registers); only the
     // stores wait.
@@ -159,53 +168,41 @@ __device__ __forceinline__ void sym_step(gptr<T> W, int64_t ldw, int n, int b, i
     // loaded and every store is made
     if (!wait_full()) return;
     if (left) {
-        // ---- left pass: one thread per column (the columns left of the block, then the block's) ----
+        // ---- left pass: one thread per column left of the block ----
         constexpr int CPI = kWave / TWM;
         const int sub = lane / TWM, tr = lane % TWM;
-        for (int c0 = tid - lane; c0 < nq + m + 1; c0 += kSymHalf) {  // the wave's first column
+        for (int c0 = tid - lane; c0 < nq; c0 += Sh::kLeft) {  // the wave's first column
             const int ci = c0 + lane;
-            if (ci < nq) {
-                if (ci != gt) {  // (the first column is in the staging block already)
-                    const gptr<T> col = at(p, k + 1 + ci);
+            if (ci < nq && ci != gt) {  // (the first column is in the staging block already)
+                const gptr<T> col = at(p, k + 1 + ci);
 #pragma unroll
-                    for (int t = 0; t <= TWM; ++t) a[t] = to_c(col[min(t, m)]);
+                for (int t = 0; t <= TWM; ++t) a[t] = to_c(col[min(t, m)]);
 #pragma unroll
-                    for (int t = 0; t <= TWM; ++t) a[t] = t <= m ? a[t] : C(0);
-                    if (taud != 0.0) apply_segment<C, TWM>(a, vs, tau, m);
-#pragma unroll
-                    for (int t = 0; t <= TWM; ++t) wblk[lane * LDB + t] = a[t];
-                }
-            } else if (ci < nq + m + 1) {
-                const int t2 = ci - nq;
-#pragma unroll
-                for (int t = 0; t <= TWM; ++t) a[t] = t <= m ? blk[t + t2 * LDB] : C(0);
+                for (int t = 0; t <= TWM; ++t) a[t] = t <= m ? a[t] : C(0);
                 if (taud != 0.0) apply_segment<C, TWM>(a, vs, tau, m);
 #pragma unroll
-                for (int t = 0; t <= TWM; ++t)
-                    if (t <= m) blk[t + t2 * LDB] = a[t];
+                for (int t = 0; t <= TWM; ++t) wblk[lane * LDB + t] = a[t];
             }
             __builtin_amdgcn_wave_barrier();
-            if (c0 < nq) {
-                const int cmax = min(nq - c0, kWave);  // columns of this wave left of the block
-                // column c0 + x starts x * rs elements after column c0
-                const Rsrc base = make_rsrc(wave_uniform(at(p, k + 1 + c0)));
+            const int cmax = min(nq - c0, kWave);  // columns of this wave
+            // column c0 + x starts x * rs elements after column c0
+            const Rsrc base = make_rsrc(wave_uniform(at(p, k + 1 + c0)));
 #pragma unroll
-                for (int u = 0; u < TWM; ++u) a[u] = wblk[(u * CPI + sub) * LDB + tr];
-                a[TWM] = wblk[lane * LDB + TWM];
-                const int o = sub * rs32 + tr;
-                // the stride is made opaque so that the per-store offsets are formed at the stores
-                int step = CPI * rs32;
-                asm volatile("" : "+s"(step));
+            for (int u = 0; u < TWM; ++u) a[u] = wblk[(u * CPI + sub) * LDB + tr];
+            a[TWM] = wblk[lane * LDB + TWM];
+            const int o = sub * rs32 + tr;
+            // the stride is made opaque so that the per-store offsets are formed at the stores
+            int step = CPI * rs32;
+            asm volatile("" : "+s"(step));
 #pragma unroll
-                for (int u = 0; u < TWM; ++u)
-                    if (tr <= m && u * CPI + sub < cmax) buf_st<T>(base, o, u * step, static_cast<T>(a[u]));
-                if (m == TWM && lane < cmax) buf_st<T>(base, lane * rs32, TWM, static_cast<T>(a[TWM]));
-            }
-            __builtin_amdgcn_wave_barrier();  // the block is rewritten by the next iteration
+            for (int u = 0; u < TWM; ++u)
+                if (tr <= m && u * CPI + sub < cmax) buf_st<T>(base, o, u * step, static_cast<T>(a[u]));
+            if (m == TWM && lane < cmax) buf_st<T>(base, lane * rs32, TWM, static_cast<T>(a[TWM]));
+            __builtin_amdgcn_wave_barrier();  // the staging block is rewritten by the next iteration
         }
-    } else {
+    } else if (right) {
         // ---- right pass below the block: one thread per row ----
-        for (int ri = gt; ri < nout; ri += kSymThreads - kSymHalf) {
+        for (int ri = gt; ri < nout; ri += Sh::kRight) {
             const gptr<T> row = at(p + m + 1 + ri, p);  // A(p+m+1+ri, p+t) = row[t * rs]
             if (ri != gt || !row_early) {  // (an early first row is updated already)
 #pragma unroll
@@ -218,21 +215,29 @@ __device__ __forceinline__ void sym_step(gptr<T> W, int64_t ldw, int n, int b, i
             for (int t = 0; t <= TWM; ++t)
                 if (t <= m) st_agent(row + (int64_t)t * rs, static_cast<T>(a[t]));
         }
-    }
-    __syncthreads();
-    // ---- the block's rows: right pass, then the row's part of the lower triangle goes back ----
-    if (tid <= m) {
-        const int ri = tid;
+    } else {
+        // ---- the block: left pass on its columns, then right pass on its rows ----
+        if (lane <= m) {
 #pragma unroll
-        for (int t = 0; t <= TWM; ++t) a[t] = t <= m ? blk[ri + t * LDB] : C(0);
-        if (taud != 0.0) apply_segment<C, TWM>(a, vs, tau, m);
+            for (int t = 0; t <= TWM; ++t) a[t] = t <= m ? blk[t + lane * LDB] : C(0);
+            if (taud != 0.0) apply_segment<C, TWM>(a, vs, tau, m);
 #pragma unroll
-        for (int t = 0; t <= TWM; ++t)
-            if (t <= ri) st_agent(at(p + ri, p + t), static_cast<T>(a[t]));
+            for (int t = 0; t <= TWM; ++t)
+                if (t <= m) blk[t + lane * LDB] = a[t];
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (lane <= m) {
+            const int ri = lane;
+#pragma unroll
+            for (int t = 0; t <= TWM; ++t) a[t] = t <= m ? blk[ri + t * LDB] : C(0);
+            if (taud != 0.0) apply_segment<C, TWM>(a, vs, tau, m);
+#pragma unroll
+            for (int t = 0; t <= TWM; ++t)
+                if (t <= ri) st_agent(at(p + ri, p + t), static_cast<T>(a[t]));
+            // column k becomes (beta, 0, ..., 0); every wave read its segment before the barrier
+            st_agent(at(p + lane, k), static_cast<T>(lane == 0 ? betad : 0.0));
+        }
     }
-    // column k becomes (beta, 0, ..., 0); every wave read its segment before the barriers above
-    if (tid >= kSymHalf && tid - kSymHalf <= m)
-        st_agent(at(p + tid - kSymHalf, k), static_cast<T>(tid == kSymHalf ? betad : 0.0));
 }
 
 // One stage; progress[r] = steps completed by sweep r, kDone once it and every
@@ -346,7 +351,10 @@ static hipError_t launch_sym_stage_t(const SymStageArgs& a, int twm, int nt, int
     return hipGetLastError();
 }
 
-int sym_stage_threads(int b, int tw) { return b + tw <= 128 ? 256 : 512; }
+int sym_stage_threads(int b, int tw) {
+    (void)tw;
+    return b <= 64 ? 256 : 512;  // the 256-thread shape: 128 left-group and 64 right-group threads
+}
 
 hipError_t launch_sym_stage(int dtype, const SymStageArgs& a, int twm, int nt, int grid, hipStream_t st) {
     return dtype == 0 ? launch_sym_stage_t<double>(a, twm, nt, grid, st) : launch_sym_stage_t<float>(a, twm, nt, grid, st);

@@ -56,11 +56,11 @@ def _gpu(bb, band, n, b, dt=torch.float64, **params):
     return d.cpu().numpy(), e.cpu().numpy()
 
 
-# (600, 128, 32) starts with a 512-thread stage (b + tw > 128) and continues with 256-thread
-# ones; (520, 250, 16) makes the left group of a 512-thread workgroup loop (b + tw > 256)
+# (600, 128, 32) starts with 512-thread stages (b > 64) and ends with 256-thread ones;
+# (700, 300, 16) makes both groups of a 512-thread workgroup loop (b - 1 > 256 columns, b > 192 rows)
 @pytest.mark.parametrize("n,b,tw", [(512, 32, 32), (700, 40, 16), (333, 17, 4), (257, 9, 8), (200, 3, 2), (150, 2, 1),
                                     (400, 64, 32), (301, 100, 24), (90, 89, 8), (1025, 48, 32), (600, 128, 32),
-                                    (520, 250, 16)])
+                                    (700, 300, 16)])
 def test_fp64_bitwise_oracle(bb, n, b, tw):
     _say("case sym fp64 n=%d b=%d tw=%d" % (n, b, tw))
     band = sym_band(n, b, seed=n + b)
