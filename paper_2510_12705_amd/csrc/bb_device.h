@@ -1,7 +1,6 @@
 // bb_device.h -- device-side building blocks for the gfx950 bulge-chasing kernels.
 //
-// Lane broadcast, the FP64 Householder generator and the TwoSum step of the
-// compensated (Dot2) sums used by the reduced-precision storage forms.
+// Lane broadcast and the FP64 Householder generator.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -193,15 +192,6 @@ __device__ __forceinline__ void house_lds(double x_lane, double x_hi, int m, dou
     tau = (bt - alpha) / bt;
     for (int i = 0; i < knt; ++i) bt = bt * safmin;
     beta = bt;
-}
-
-// ---------------------------------------------------------------------------
-// Dot products: plain FMA chain (FP64) and Ogita-Rump-Oishi Dot2 (FP32).
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
-    s = a + b;
-    float bb = s - a;
-    e = (a - (s - bb)) + (b - bb);
 }
 
 }  // namespace bbk

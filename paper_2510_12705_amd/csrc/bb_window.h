@@ -121,8 +121,11 @@ __device__ __forceinline__ void st_agent(gptr<T> p, T v) {
 //   FP64 storage: the dot is summed left to right with separate multiply and add
 //   and the update is a - (tau w) v, i.e. the same IEEE operations as a plain
 //   sequential implementation (no fused multiply-add; contraction is off).
-//   FP32 / FP16 storage: compensated Dot2 (Ogita, Rump, Oishi 2005) with
-//   TwoSum and an FMA-based TwoProduct, then a - fma(tau w, v).
+//   FP32 / FP16 storage: single-precision arithmetic, as the paper computes in
+//   the storage type: the dot as a chain of fused multiply-adds, then
+//   a - fma(tau w, v).  (A compensated Dot2 dot was the earlier form: its
+//   three dependent operations per term make the chain, which is on the
+//   critical path of every task, about three times longer.)
 // ---------------------------------------------------------------------------
 template <typename C, int TWM>
 __device__ __forceinline__ void apply_segment(C (&av)[TWM + 1], const C (&vs)[TWM + 1], C tau, int m) {
@@ -135,16 +138,10 @@ __device__ __forceinline__ void apply_segment(C (&av)[TWM + 1], const C (&vs)[TW
 #pragma unroll
         for (int t = 0; t <= TWM; ++t) av[t] = av[t] - tw * vs[t];
     } else {
-        float s = 0.f, comp = 0.f;
+        float s = 0.f;
 #pragma unroll
-        for (int t = 0; t <= TWM; ++t) {
-            const float pr = av[t] * vs[t];
-            const float ep = fmaf(av[t], vs[t], -pr);
-            float es;
-            two_sum(s, pr, s, es);
-            comp = comp + (es + ep);
-        }
-        const float tw = tau * (s + comp);
+        for (int t = 0; t <= TWM; ++t) s = fmaf(av[t], vs[t], s);
+        const float tw = tau * s;
 #pragma unroll
         for (int t = 0; t <= TWM; ++t) av[t] = fmaf(-tw, vs[t], av[t]);
     }
