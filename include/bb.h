@@ -14,8 +14,11 @@
  *       A(i, j) = band[(b + i - j) + j * ldband],  max(0, j - b) <= i <= j,
  *     ldband >= b + 1.  Entries above row 0 are ignored.  `band` is read only.
  *   - Storage type (bb_dtype_t): BB_F64 -> double, BB_F32 -> float,
- *     BB_F16 -> IEEE binary16.  The band is stored and updated in this type;
- *     Householder reflectors (norm, beta, tau) are always generated in FP64.
+ *     BB_F16 -> IEEE binary16.  The band is stored in this type; updates are
+ *     computed in FP64 for BB_F64 (sequential sums, no FMA: bitwise the plain
+ *     definition) and in FP32 with fused multiply-add dot products for BB_F32
+ *     and BB_F16, then rounded to the storage type.  Householder reflectors
+ *     (norm, beta, tau) are always generated in FP64.
  *     BB_F16 keeps a power-of-two scale per bandwidth-reduction stage.
  *   - Outputs: d (n doubles) = diagonal, e (n - 1 doubles) = super-diagonal of
  *     B, always FP64.  Signs of d, e are not unique; |d|, |e| are.
