@@ -24,8 +24,9 @@
 // operations in the same order as under the sequential order; the dot product
 // and the update are the plain sequential ones (no fused multiply-add), so FP64
 // results equal a plain sequential accumulation bit for bit (up to the sign of
-// zero).  Entries of v above m are logged as 0, and columns beyond n - 1 are
-// held as 0 and never stored.
+// zero; a reflector with tau = 0 is applied as the identity it is).  Entries of
+// v above m are logged as 0; window slots past column n - 1 hold a copy of
+// column n - 1, meet only those zero entries, and are never stored.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -88,7 +89,11 @@ __global__ __launch_bounds__(64) void bb_backtransform(double* __restrict__ Xv, 
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool row = i < n;  // lanes past the last row compute on zeros and store nothing
     gptr_v<double> xi = (gptr_v<double>)(X + (row ? i : 0));
-    auto ld = [&](int col) -> double { return (row && col < n) ? xi[(int64_t)col * ldx] : 0.0; };
+    // Column loads are never predicated (lanes past the last row read row 0, columns past
+    // n - 1 read column n - 1), so they land in their registers without a select and
+    // their latency stays hidden until first use.  Such values only ever meet zero
+    // reflector entries (entries above m are logged as 0) and are never stored.
+    auto ld = [&](int col) -> double { return xi[(int64_t)min(col, n - 1) * ldx]; };
     // the block of sweeps r0 .. r0+U-1: entries [u][t], zero beyond wlog or rcount
     auto fetch = [&](const double* __restrict__ slots, int r0, int rcount, double (&q)[Q]) {
 #pragma unroll
@@ -123,35 +128,33 @@ __global__ __launch_bounds__(64) void bb_backtransform(double* __restrict__ Xv, 
         for (int rb = 0;; rb += U) {
             fetch(slots, rb + U, rcount, q);  // the next block's reflectors
             const double* vb = vbuf + buf * BE;
+            // Every reflector of the block is applied unconditionally: those past rcount
+            // (and tau = 0 ones) have tau = 0 and v = 0 in the staged log, so they leave
+            // the row unchanged (up to the sign of a zero), and no branch separates the
+            // LDS reads of one reflector from the next.
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int r = rb + u;
-                if (r < rcount) {
-                    const double* sl = vb + u * W;
-                    const double tau = sl[0];
-                    if (tau != 0.0) {
-                        double w = 0.0;
-                        w = w + x[u] * 1.0;
+                const double* sl = vb + u * W;
+                const double tau = sl[0];
+                double w = 0.0;
+                w = w + x[u] * 1.0;
 #pragma unroll
-                        for (int t = 1; t < W; ++t) w = w + x[u + t] * sl[t];
-                        const double tw = tau * w;
-                        x[u] = x[u] - tw * 1.0;
+                for (int t = 1; t < W; ++t) w = w + x[u + t] * sl[t];
+                const double tw = tau * w;
+                x[u] = x[u] - tw * 1.0;
 #pragma unroll
-                        for (int t = 1; t < W; ++t) x[u + t] = x[u + t] - tw * sl[t];
-                    }
-                    // column p leaves the window for good in this step; column p + R enters
-                    const int p = p0 + r;
-                    if (row) xi[(int64_t)p * ldx] = x[u];
-                    x[u + R] = ld(p + R);
-                }
+                for (int t = 1; t < W; ++t) x[u + t] = x[u + t] - tw * sl[t];
+                // column p leaves the window for good in this step; column p + R enters
+                const int p = p0 + rb + u;
+                if (row && p < n) xi[(int64_t)p * ldx] = x[u];
+                x[u + R] = ld(p + R);
             }
             if (rb + U >= rcount) {
-                // the window's columns p0 + rcount .. + R - 1 sit in x[rcount - rb ..]
-                const int done = rcount - rb;
+                // the window's remaining columns p0 + rb + U .. + R - 1 sit in x[U ..]
 #pragma unroll
-                for (int s = 0; s < R + U; ++s) {
+                for (int s = U; s < R + U; ++s) {
                     const int col = p0 + rb + s;
-                    if (s >= done && s < done + R && row && col < n) xi[(int64_t)col * ldx] = x[s];
+                    if (row && col < n) xi[(int64_t)col * ldx] = x[s];
                 }
                 break;
             }
