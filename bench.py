@@ -118,6 +118,17 @@ def de_sha256(d, e):
     return h.hexdigest()
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(band, n, b, tw, group, max_threads, full_limit_s=45.0):
     """The FP64 oracle run as a lag-rule wavefront on the host's threads.  Its
     first stage is timed first; if the whole reduction is then expected to take
@@ -131,6 +142,7 @@ def cpu_baseline(band, n, b, tw, group, max_threads, full_limit_s=45.0):
     except AttributeError:
         avail = os.cpu_count() or 1
     threads = max(1, min(max_threads, avail))
+    host = {"cpu_model": _cpu_model(), "nproc": os.cpu_count(), "affinity": avail}
     t0 = time.perf_counter()
     _, _, used = oracle.reduce_wavefront(band, n, b, tw, threads=threads, group=group, max_stages=1)
     dt1 = time.perf_counter() - t0
@@ -147,11 +159,11 @@ def cpu_baseline(band, n, b, tw, group, max_threads, full_limit_s=45.0):
                 "sample": "the whole n=%d, b=%d reduction (TW=%d, %d stages): FP64 oracle as a lag-rule wavefront "
                           "on %d host threads, groups of %d sweeps; %.2f s (first-stage probe %.2f s)"
                           % (n, b, tw, len(bb.plan(b, tw)), used, group, dt, dt1),
-                "de_bitwise_oracle_hash": (de_sha256(d, e) == rec["de_sha256"]) if rec else None}
+                "de_bitwise_oracle_hash": (de_sha256(d, e) == rec["de_sha256"]) if rec else None, "host": host}
     return {"value": dt1 * scale * 1e3, "unit": "ms", "cores": used, "kind": "oracle",
             "sample": "FP64 oracle as a lag-rule wavefront on %d host threads (groups of %d sweeps), first stage "
                       "(b=%d -> %d, TW=%d) of the full n=%d reduction: %.2f s, scaled x%.2f by the algorithmic "
-                      "bytes of all stages" % (used, group, b, c, tw, n, dt1, scale)}
+                      "bytes of all stages" % (used, group, b, c, tw, n, dt1, scale), "host": host}
 
 
 def main():
