@@ -166,6 +166,31 @@ def cpu_baseline(band, n, b, tw, group, max_threads, full_limit_s=45.0):
                       "bytes of all stages" % (used, group, b, c, tw, n, dt1, scale), "host": host}
 
 
+def cpu_other_workloads(tw, group, max_threads):
+    """Whole FP64 reductions by the CPU oracle wavefront on the other synthetic workloads, each
+    checked against the stored oracle hash where one exists."""
+    import oracle
+    from paper_2510_12705_amd import inputs
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    threads = max(1, min(max_threads, avail))
+    res = {}
+    for name in ("n512_b32", "n8192_b64", "n16384_b16_uniform", "n16384_b32_uniform", "n16384_b64_uniform",
+                 "n16384_b128_uniform", "n16384_b256_uniform"):
+        _, wn, wb, _, _ = inputs.WORKLOADS[name]
+        bd = inputs.workload(name)
+        t0 = time.perf_counter()
+        d, e, used = oracle.reduce_wavefront(bd, wn, wb, tw, threads=threads, group=group)
+        dt = time.perf_counter() - t0
+        rec, _ = golden("%s_f64_tw%d" % (name, tw))
+        res[name] = {"ms": round(dt * 1e3, 1), "threads": used,
+                     "de_bitwise_oracle_hash": (de_sha256(d, e) == rec["de_sha256"]) if rec else None}
+        print("[bench] cpu %s: %.2f s" % (name, dt), file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +202,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=16)
     ap.add_argument("--cpu-group", type=int, default=8)
+    ap.add_argument("--cpu-configs", action="store_true",
+                    help="also time the CPU oracle wavefront on the other workloads (n=512 b=32, n=8192 b=64, "
+                         "n=16384 b=16..256)")
     ap.add_argument("--autotune", action="store_true",
                     help="run the library's timed parameter search for each storage type before timing")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -280,6 +308,8 @@ def main():
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle wavefront, first stage) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(band, n, b, p.tw, args.cpu_group, args.cpu_threads)
+        if args.cpu_configs:
+            out["cpu_baseline_other_workloads"] = cpu_other_workloads(p.tw, args.cpu_group, args.cpu_threads)
     dn = d.cpu().numpy()
     en = e[: n - 1].cpu().numpy()
     rec, _ = golden("n%d_b%d_f64_tw%d" % (n, b, p.tw))

@@ -4,6 +4,7 @@
     python -m paper_2510_12705_amd.measure c5   # 512 ragged FP32 bands: one batched call vs a loop
     python -m paper_2510_12705_amd.measure sigma  # sigma of the n = 32768 bidiagonal on the device
     python -m paper_2510_12705_amd.measure sym    # symmetric band -> tridiagonal, FP64 / FP32 storage
+    python -m paper_2510_12705_amd.measure small  # n = 512, b = 32 and n = 8192, b = 64, N(0,1) bands
 
 Each case is timed as the best of two runs after one warm-up (host wall clock
 around the call and a device synchronisation), in the default launch
@@ -109,6 +110,26 @@ def ragged_batch(count=512, seed=5):
     bb.release()
 
 
+def small_workloads(names=("n512_b32", "n8192_b64")):
+    """The two smaller N(0,1) workloads (n = 512, b = 32 and n = 8192, b = 64), FP64 and
+    FP32 storage, best of five after a warm-up."""
+    import torch
+
+    from . import bb, inputs
+    bb.reset_params()
+    for name in names:
+        _, n, b, _, _ = inputs.WORKLOADS[name]
+        band = torch.from_numpy(inputs.workload(name)).cuda()
+        out = []
+        for dt, elem in ((torch.float64, 8), (torch.float32, 4)):
+            t = band.to(dt)
+            ms = _best_ms(torch, lambda: bb.bb_reduce(t, n, b), reps=5)
+            alg = bb.model_bytes(n, b, elem, TW_REF[elem])
+            out.append("%s %.2f ms (%.1f%% roofline)" % (str(dt).split(".")[-1], ms,
+                                                            100 * alg / (ms / 1e3) / PEAK_BYTES_PER_S))
+        print("n=%d b=%d: %s" % (n, b, " | ".join(out)), flush=True)
+
+
 def symmetric(cases=((8192, 64), (32768, 128))):
     """The symmetric band -> tridiagonal reduction (bb_sym_reduce), FP64 and FP32
     storage, N(0,1) lower bands: time and % of roofline by the symmetric
@@ -169,4 +190,5 @@ def bidiag_sigma(n=32768, b=128):
 
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "c4"
-    {"c4": bandwidth_sweep, "c5": ragged_batch, "sigma": bidiag_sigma, "sym": symmetric}[what]()
+    {"c4": bandwidth_sweep, "c5": ragged_batch, "sigma": bidiag_sigma, "sym": symmetric,
+     "small": small_workloads}[what]()
