@@ -5,6 +5,7 @@
     python -m paper_2510_12705_amd.measure sigma  # sigma of the n = 32768 bidiagonal on the device
     python -m paper_2510_12705_amd.measure sym    # symmetric band -> tridiagonal, FP64 / FP32 storage
     python -m paper_2510_12705_amd.measure small  # n = 512, b = 32 and n = 8192, b = 64, N(0,1) bands
+    python -m paper_2510_12705_amd.measure vectors  # reduction plus U and V (FP64), n = 8192 and 16384
 
 Each case is timed as the best of two runs after one warm-up (host wall clock
 around the call and a device synchronisation), in the default launch
@@ -130,6 +131,38 @@ def small_workloads(names=("n512_b32", "n8192_b64")):
         print("n=%d b=%d: %s" % (n, b, " | ".join(out)), flush=True)
 
 
+def vectors(cases=("n8192_b64", "n16384_b128_uniform")):
+    """bb_reduce_vectors (FP64; the reduction logs its reflectors, then U and V are
+    formed from the identity) against bb_reduce alone on the same band.  The
+    back-transformation's arithmetic: every reflector of a stage meets every row of
+    its factor once, a dot and an update of its m + 1 entries (4 (m + 1) flops)."""
+    import torch
+
+    from . import bb, inputs
+    bb.reset_params()
+    for name in cases:
+        _, n, b, _, _ = inputs.WORKLOADS[name]
+        band = torch.from_numpy(inputs.workload(name)).cuda()
+        t_red = _best_ms(torch, lambda: bb.bb_reduce(band, n, b))
+        t_vec = _best_ms(torch, lambda: bb.bb_reduce_vectors(band, n, b))
+        flops = 0.0
+        tw = 32
+        bs = b
+        while bs > 1:
+            t = min(tw, bs - 1)
+            c = bs - t
+            for r in range(0, n - c - 1):
+                steps = 1 + (n - 2 - r - c) // bs
+                # step 0 has m = b - c = t entries past the first; later steps min(t, n - 1 - p)
+                flops += 2 * steps * n * 4 * (t + 1)
+            bs = c
+        back_ms = t_vec - t_red
+        print("n=%d b=%d: reduction %.1f ms, with U and V %.1f ms (back-transformation %.1f ms, %.0f GFLOP/s)" % (
+            n, b, t_red, t_vec, back_ms, flops / (back_ms / 1e3) / 1e9), flush=True)
+        del band
+        torch.cuda.empty_cache()
+
+
 def symmetric(cases=((8192, 64), (32768, 128))):
     """The symmetric band -> tridiagonal reduction (bb_sym_reduce), FP64 and FP32
     storage, N(0,1) lower bands: time and % of roofline by the symmetric
@@ -191,4 +224,4 @@ def bidiag_sigma(n=32768, b=128):
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "c4"
     {"c4": bandwidth_sweep, "c5": ragged_batch, "sigma": bidiag_sigma, "sym": symmetric,
-     "small": small_workloads}[what]()
+     "small": small_workloads, "vectors": vectors}[what]()
