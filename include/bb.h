@@ -155,7 +155,13 @@ int bb_reduce_noalloc(int64_t n, int64_t b, bb_dtype_t dtype, const void *band, 
  * ldband=5, d=6, e=7, U=8, ldu=9, V=10, ldv=11.  Working memory (stream-ordered,
  * freed by the call) is bb_workspace_bytes plus the reflector log: per stage
  * (b_s, TW_s), 2 (n - c_s - 1)(1 + (n - 2 - c_s) / b_s)(TW + 1) doubles, about
- * 100 MB at n = 2048, b = 64 and 37 GB at n = 32768, b = 128.
+ * 100 MB at n = 2048, b = 64 and 37 GB at n = 32768, b = 128.  The accumulation
+ * of stage s's reflectors runs on a second stream that the library owns (one
+ * per device, default priority, kept until the process ends) while the
+ * reduction continues with the next stage on `stream`; the call orders that
+ * stream after the work already queued on `stream` and `stream` after it, so
+ * the results, as with every call here, are complete when `stream` reaches the
+ * end of the call.
  */
 int bb_reduce_vectors(int64_t n, int64_t b, bb_dtype_t dtype, const void *band, int64_t ldband,
                       double *d, double *e, double *U, int64_t ldu, double *V, int64_t ldv,

@@ -44,6 +44,7 @@ struct DeviceState {
     int nxcd = 1;                  // XCDs (accelerator complex dies), each with its own L2
     int* err_dev = nullptr;        // this device's copy of g_err_word
     char* scratch_dev = nullptr;   // this device's copy of `scratch` (bb_reduce_noalloc)
+    hipStream_t aux = nullptr;     // second stream of bb_reduce_vectors (default priority)
 };
 
 std::mutex g_mu;
@@ -522,6 +523,7 @@ struct VecLog {
     std::vector<int64_t> off;     // per stage: offset of its slots (doubles)
     std::vector<int> nsteps;      // per stage: steps of its longest sweep (sweep 0)
     int64_t doubles = 0;          // total size
+    std::vector<hipEvent_t> stage_done;  // if set: recorded on the call's stream after stage s
 };
 
 static VecLog veclog_layout(int64_t n, int64_t bb, int tw) {
@@ -577,7 +579,11 @@ static int enqueue_call(const Call& c, const void* band, int64_t ldband, double*
         a.xcd_run = std::max(L.xcd_run, 1);
         a.vlog = vl && vl->base ? vl->base + vl->off[(size_t)s] : nullptr;
         a.wlog = vl ? vl->wlog : 0;
-        if (a.nsweeps == 0) continue;
+        hipEvent_t done_ev = vl && (size_t)s < vl->stage_done.size() ? vl->stage_done[(size_t)s] : nullptr;
+        if (a.nsweeps == 0) {
+            if (done_ev) rc = check_hip(hipEventRecord(done_ev, st));
+            continue;
+        }
         if (dtype == BB_F16) rc = check_hip(bbk::launch_f16_rescale(W, n * ws.ldw, f16_amax + s, f16_exps, s, st));
         if (rc) break;
         const int twm = bbp::kernel_twm(sg.tw);
@@ -606,6 +612,7 @@ static int enqueue_call(const Call& c, const void* band, int64_t ldband, double*
             }
         }
         rc = check_hip(bbk::launch_stage(dtype, a, twm, ntl_s, lanes_s, grid, st));
+        if (!rc && done_ev) rc = check_hip(hipEventRecord(done_ev, st));
         if (timed) {
             (void)hipEventRecord(e1, st);
             std::lock_guard<std::mutex> lk(g_mu);
@@ -685,24 +692,65 @@ int bb_reduce_vectors(int64_t n, int64_t b, bb_dtype_t dtype, const void* band, 
     rc = prepare_call(n, b, dtype, ds, current_params(), true, &c);
     if (rc) return rc;
     VecLog vl = veclog_layout(n, c.bb, c.L.tw);
+    // The back-transformation of stage s needs only stage s's reflector log (and the
+    // factors after stage s-1's), so it runs on a second stream while the reduction
+    // goes on with stage s+1: the stage kernels are latency-bound and leave most of
+    // the chip to it.  Events order the two streams (fork after the work already on
+    // `stream`, one event per stage, join before the workspace is freed), which also
+    // holds under stream capture.
+    hipStream_t aux = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!ds->aux && hipStreamCreateWithFlags(&ds->aux, hipStreamNonBlocking) != hipSuccess) ds->aux = nullptr;
+        aux = ds->aux;
+    }
+    if (!aux) return BB_ERR_HIP;
+    const size_t nst = vl.off.size();
+    std::vector<hipEvent_t> evs(nst + 2, nullptr);  // stage events, fork, join
+    auto destroy_events = [&]() {
+        for (hipEvent_t ev : evs)
+            if (ev) (void)hipEventDestroy(ev);
+    };
+    for (hipEvent_t& ev : evs)
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            ev = nullptr;
+            destroy_events();
+            return BB_ERR_HIP;
+        }
     const size_t total = c.ws.total + align_up(sizeof(double) * (size_t)vl.doubles, 256);
     void* base = nullptr;
-    if (hipMallocAsync(&base, total, st) != hipSuccess) return BB_ERR_NOMEM;
+    if (hipMallocAsync(&base, total, st) != hipSuccess) {
+        destroy_events();
+        return BB_ERR_NOMEM;
+    }
     vl.base = vl.doubles > 0 ? reinterpret_cast<double*>(static_cast<char*>(base) + c.ws.total) : nullptr;
-    rc = enqueue_call(c, band, ldband, d, e, st, ds, static_cast<char*>(base), true, &vl);
-    if (!rc && U) rc = check_hip(bbk::launch_identity(U, n, ldu, st));
-    if (!rc && V) rc = check_hip(bbk::launch_identity(V, n, ldv, st));
+    vl.stage_done.assign(evs.begin(), evs.begin() + nst);
+    hipEvent_t fork = evs[nst], join = evs[nst + 1];
+    rc = check_hip(hipEventRecord(fork, st));
+    const bool forked = !rc && hipStreamWaitEvent(aux, fork, 0) == hipSuccess;
+    if (!forked && !rc) rc = BB_ERR_HIP;
+    if (!rc && U) rc = check_hip(bbk::launch_identity(U, n, ldu, aux));
+    if (!rc && V) rc = check_hip(bbk::launch_identity(V, n, ldv, aux));
+    if (!rc) rc = enqueue_call(c, band, ldband, d, e, st, ds, static_cast<char*>(base), true, &vl);
     if (!rc && vl.base) {
         size_t s = 0;
-        for (bbp::Stage sg = bbp::stage_first(c.bb, c.L.tw); !rc; sg = bbp::stage_next(sg, c.L.tw), ++s) {
+        for (bbp::Stage sg = bbp::stage_first(c.bb, c.L.tw); !rc && s < nst; sg = bbp::stage_next(sg, c.L.tw), ++s) {
             const int nsw = (int)std::max<int64_t>(n - sg.c - 1, 0);
-            rc = check_hip(bbk::launch_backtransform(V, ldv, U, ldu, (int)n, sg.b, sg.tw, sg.c, nsw, vl.nsteps[s],
-                                                     vl.base + vl.off[s], vl.wlog, st));
+            rc = check_hip(hipStreamWaitEvent(aux, vl.stage_done[s], 0));
+            if (!rc)
+                rc = check_hip(bbk::launch_backtransform(V, ldv, U, ldu, (int)n, sg.b, sg.tw, sg.c, nsw,
+                                                         vl.nsteps[s], vl.base + vl.off[s], vl.wlog, aux));
             if (sg.c <= 1) break;
         }
     }
+    if (forked) {  // always joined, so that nothing on `aux` outlives the workspace
+        const int jr = check_hip(hipEventRecord(join, aux));
+        const int jw = jr ? jr : check_hip(hipStreamWaitEvent(st, join, 0));
+        if (!rc) rc = jw;
+    }
     hipError_t fe = hipFreeAsync(base, st);
     if (!rc && fe != hipSuccess) rc = BB_ERR_HIP;
+    destroy_events();
     return rc;
 }
 

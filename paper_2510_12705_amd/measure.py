@@ -132,10 +132,12 @@ def small_workloads(names=("n512_b32", "n8192_b64")):
 
 
 def vectors(cases=("n8192_b64", "n16384_b128_uniform")):
-    """bb_reduce_vectors (FP64; the reduction logs its reflectors, then U and V are
-    formed from the identity) against bb_reduce alone on the same band.  The
-    back-transformation's arithmetic: every reflector of a stage meets every row of
-    its factor once, a dot and an update of its m + 1 entries (4 (m + 1) flops)."""
+    """bb_reduce_vectors (FP64; the reduction logs its reflectors, U and V are
+    formed from the identity, stage by stage beside the reduction) against
+    bb_reduce alone on the same band; the difference is the time the
+    back-transformation adds.  Its arithmetic: every reflector of a stage meets
+    every row of its factor once, a dot and an update of its m + 1 entries
+    (4 (m + 1) flops), counted over that added time."""
     import torch
 
     from . import bb, inputs
@@ -157,7 +159,7 @@ def vectors(cases=("n8192_b64", "n16384_b128_uniform")):
                 flops += 2 * steps * n * 4 * (t + 1)
             bs = c
         back_ms = t_vec - t_red
-        print("n=%d b=%d: reduction %.1f ms, with U and V %.1f ms (back-transformation %.1f ms, %.0f GFLOP/s)" % (
+        print("n=%d b=%d: reduction %.1f ms, with U and V %.1f ms (added %.1f ms, %.0f GFLOP/s over it)" % (
             n, b, t_red, t_vec, back_ms, flops / (back_ms / 1e3) / 1e9), flush=True)
         del band
         torch.cuda.empty_cache()
