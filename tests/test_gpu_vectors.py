@@ -131,3 +131,30 @@ def test_one_factor_only_and_small_shapes(bb):
         do, eo, Uo, Vo = oracle.reduce(band, n, b, tw, want_uv=True)
         assert np.array_equal(d, do) and np.array_equal(e, eo), (n, b)
         assert np.array_equal(U, Uo) and np.array_equal(V, Vo), (n, b, bq)
+
+
+def test_factors_on_a_side_stream_are_complete_when_that_stream_is(bb):
+    """The accumulation runs on a second, library-owned stream beside the reduction
+    and is joined back into the caller's stream: on a non-default stream, waiting
+    for that stream alone must give the factors of a default-stream call, bitwise,
+    also when the caller reuses the output buffers right away."""
+    n, b = 1500, 48
+    _say("case vectors side stream n=%d b=%d" % (n, b))
+    band = inputs.band_normal(n, b, seed=11)
+    t = torch.from_numpy(np.ascontiguousarray(band)).to("cuda:0")
+    bb.reset_params()
+    d0, e0, U0, V0 = bb.bb_reduce_vectors(t, n, b)
+    torch.cuda.synchronize()
+    ref = [x.cpu().numpy() for x in (d0, e0, U0, V0)]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        d, e, U, V = bb.bb_reduce_vectors(t, n, b, stream=s)
+        Uc, Vc = U.clone(), V.clone()   # queued on s right behind the call
+        U.zero_()
+        V.zero_()
+    s.synchronize()
+    assert bb.stream_status(s) == 0
+    got = [x.cpu().numpy() for x in (d, e, Uc, Vc)]
+    for a, r in zip(got, ref):
+        assert np.array_equal(a, r)
