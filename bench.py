@@ -212,8 +212,9 @@ def main():
                          "against which HBM byte counters are calibrated)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this benchmark runs on exactly one GPU (the reduction of one band is a single-GPU "
-              "pipeline; see DESIGN.md for how it would shard); got --gpus %d" % args.gpus, file=sys.stderr)
+        print("bench.py: this benchmark runs on exactly one GPU (the reduction of one band is one pipeline "
+              "of dependent sweeps on one device; independent bands would go to separate GPUs); got --gpus %d"
+              % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
