@@ -16,9 +16,11 @@
 // Step geometry of sweep r in a stage (b, tw, c) (0-based, derived from Alg. 1):
 //   step 0 : k = r,               p = r + c, m = min(r + b, n-1) - p
 //   step j : k = r + c + (j-1) b, p = k + b, m = min(tw, n-1-p),  j = 1 .. J-1
-// Right task of a step (Alg. 1 first HH line, Alg. 2 lines 3-13): reflector from
-// A[k, p..p+m], applied to rows k+1 .. p+m.  Left task (second HH line, Alg. 2
-// line 15): reflector from A[p..p+m, p], applied to columns p+1 .. min(p+m+b, n-1).
+// Right task of a step (the first of the two Householder applications of a step
+// in Algorithm 1; the row reflector and its update in Algorithm 2): reflector from
+// A[k, p..p+m], applied to rows k+1 .. p+m.  Left task (the second application;
+// Algorithm 2's column reflector): reflector from A[p..p+m, p], applied to columns
+// p+1 .. min(p+m+b, n-1).
 //
 // Scheduling: half-step h = 2j is the right task of step j, h = 2j+1 the left
 // one.  Half-step h of sweep r waits until sweep r-1 has completed h + H half-
