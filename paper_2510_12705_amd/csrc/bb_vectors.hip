@@ -166,6 +166,118 @@ __global__ __launch_bounds__(64) void bb_backtransform(double* __restrict__ Xv, 
     }
 }
 
+// Two steps at a time on two waves (TWM <= 32): wave 0 of a workgroup runs step
+// j, wave 1 step j-1, on the same 64 rows, each with its own window and
+// reflector stream exactly as above, in block iterations that end with a
+// workgroup barrier (which also makes every store of the iteration visible to
+// the other wave).  In iteration it wave 0 applies sweeps it U .. it U + U - 1 and
+// wave 1 sweeps (it - lag) U ...  Wave 1's window then lies left of every column
+// wave 0 holds (lag U >= U + R - b), i.e. on columns wave 0 stored in earlier
+// iterations, and two reflectors of the two steps that share a column (r' >=
+// r + b - m > r) are met in the reduction's order; with no lag, b - m >= U puts
+// them in different iterations.  Each row sees the same operations in the same
+// order as with one wave, so the result is bitwise the same.
+template <int TWM>
+__global__ __launch_bounds__(128) void bb_backtransform_2w(double* __restrict__ Xv, int64_t ldv,
+                                                           double* __restrict__ Xu, int64_t ldu, int n, int b, int c,
+                                                           int nsweeps, int nsteps, const double* __restrict__ log,
+                                                           int wlog) {
+    constexpr int W = TWM + 1;
+    constexpr int R = W + ring_ahead<TWM>();
+    constexpr int U = kBlk;
+    constexpr int BE = U * W;
+    constexpr int Q = (BE + kWaveLanes - 1) / kWaveLanes;
+    extern __shared__ double vbuf[];  // [wave][2][U][W]
+    double* __restrict__ X = blockIdx.y == 0 ? Xv : Xu;
+    const int64_t ldx = blockIdx.y == 0 ? ldv : ldu;
+    if (!X) return;
+    const int wv = threadIdx.x / kWaveLanes;
+    const int lane = threadIdx.x - wv * kWaveLanes;
+    const int64_t side_slots = (int64_t)nsteps * nsweeps;
+    const double* __restrict__ lg = log + (blockIdx.y == 0 ? 0 : side_slots * wlog);
+    const int64_t i = (int64_t)blockIdx.x * kWaveLanes + lane;
+    const bool row = i < n;
+    gptr_v<double> xi = (gptr_v<double>)(X + (row ? i : 0));
+    auto ld = [&](int col) -> double { return xi[(int64_t)min(col, n - 1) * ldx]; };
+    auto fetch = [&](const double* __restrict__ slots, int r0, int rcount, double (&q)[Q]) {
+#pragma unroll
+        for (int z = 0; z < Q; ++z) {
+            const int e = lane + kWaveLanes * z;
+            const int u = e / W, t = e - u * W;
+            const int r = r0 + u;
+            q[z] = (e < BE && t < wlog && r < rcount) ? slots[(int64_t)r * wlog + t] : 0.0;
+        }
+    };
+    double* const vb = vbuf + wv * 2 * BE;
+    auto stage = [&](int buf, const double (&q)[Q]) {
+#pragma unroll
+        for (int z = 0; z < Q; ++z) {
+            const int e = lane + kWaveLanes * z;
+            if (e < BE) vb[buf * BE + e] = q[z];
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
+    const int lag = max(0, (U + R - b + U - 1) / U);
+    for (int j = nsteps - 1; j >= 0; j -= 2) {
+        const int rca = min(n - 1 - c - j * b, nsweeps);  // sweeps with p <= n - 2
+        const int rcb = j >= 1 ? min(n - 1 - c - (j - 1) * b, nsweeps) : 0;
+        if (rca <= 0 && rcb <= 0) continue;
+        const int la = rca > 0 && rcb > 0 ? lag : 0;
+        const int its = max((max(rca, 0) + U - 1) / U, la + (max(rcb, 0) + U - 1) / U);  // same on both waves
+        const int jj = wv == 0 ? j : j - 1;
+        const int rc = wv == 0 ? rca : rcb;
+        const int sh = wv == 0 ? 0 : la;
+        const int p0 = c + jj * b;
+        const double* __restrict__ slots = lg + (int64_t)max(jj, 0) * nsweeps * wlog;
+        double x[R + U];
+        double q[Q];
+        int buf = 0;
+        for (int it = 0; it < its; ++it) {
+            const int rb = (it - sh) * U;
+            if (rb >= 0 && rb < rc) {  // wave-uniform
+                if (rb == 0) {
+#pragma unroll
+                    for (int t = 0; t < R; ++t) x[t] = ld(p0 + t);
+                    fetch(slots, 0, rc, q);
+                    stage(0, q);
+                    buf = 0;
+                }
+                fetch(slots, rb + U, rc, q);
+                const double* cur = vb + buf * BE;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const double* sl = cur + u * W;
+                    const double tau = sl[0];
+                    double w = 0.0;
+                    w = w + x[u] * 1.0;
+#pragma unroll
+                    for (int t = 1; t < W; ++t) w = w + x[u + t] * sl[t];
+                    const double tw = tau * w;
+                    x[u] = x[u] - tw * 1.0;
+#pragma unroll
+                    for (int t = 1; t < W; ++t) x[u + t] = x[u + t] - tw * sl[t];
+                    const int p = p0 + rb + u;
+                    if (row && p < n) xi[(int64_t)p * ldx] = x[u];
+                    x[u + R] = ld(p + R);
+                }
+                if (rb + U >= rc) {
+#pragma unroll
+                    for (int s2 = U; s2 < R + U; ++s2) {
+                        const int col = p0 + rb + s2;
+                        if (row && col < n) xi[(int64_t)col * ldx] = x[s2];
+                    }
+                } else {
+                    stage(buf ^ 1, q);
+                    buf ^= 1;
+#pragma unroll
+                    for (int t = 0; t < R; ++t) x[t] = x[t + U];
+                }
+            }
+            __syncthreads();  // this iteration's stores are visible to the other wave
+        }
+    }
+}
+
 hipError_t launch_identity(double* X, int64_t n, int64_t ldx, hipStream_t st) {
     if (!X || n <= 0) return hipSuccess;
     const int grid = (int)std::min<int64_t>((n * n + 255) / 256, 8192);
@@ -181,13 +293,21 @@ static void launch_bt(dim3 grid, hipStream_t st, double* Xv, int64_t ldv, double
                        nsteps, log, wlog);
 }
 
+template <int TWM>
+static void launch_2w(dim3 grid, hipStream_t st, double* Xv, int64_t ldv, double* Xu, int64_t ldu, int n, int b,
+                      int c, int nsweeps, int nsteps, const double* log, int wlog) {
+    const size_t lds = sizeof(double) * 4 * (size_t)kBlk * (TWM + 1);
+    hipLaunchKernelGGL(bb_backtransform_2w<TWM>, grid, dim3(2 * kWaveLanes), lds, st, Xv, ldv, Xu, ldu, n, b, c,
+                       nsweeps, nsteps, log, wlog);
+}
+
 hipError_t launch_backtransform(double* Xv, int64_t ldv, double* Xu, int64_t ldu, int n, int b, int tw, int c,
                                 int nsweeps, int nsteps, const double* log, int wlog, hipStream_t st) {
     if ((!Xv && !Xu) || n <= 1 || nsweeps <= 0 || nsteps <= 0) return hipSuccess;
     const dim3 grid((unsigned)((n + kWaveLanes - 1) / kWaveLanes), 2);
-    if (tw <= 8) launch_bt<8>(grid, st, Xv, ldv, Xu, ldu, n, b, c, nsweeps, nsteps, log, wlog);
-    else if (tw <= 16) launch_bt<16>(grid, st, Xv, ldv, Xu, ldu, n, b, c, nsweeps, nsteps, log, wlog);
-    else if (tw <= 32) launch_bt<32>(grid, st, Xv, ldv, Xu, ldu, n, b, c, nsweeps, nsteps, log, wlog);
+    if (tw <= 8) launch_2w<8>(grid, st, Xv, ldv, Xu, ldu, n, b, c, nsweeps, nsteps, log, wlog);
+    else if (tw <= 16) launch_2w<16>(grid, st, Xv, ldv, Xu, ldu, n, b, c, nsweeps, nsteps, log, wlog);
+    else if (tw <= 32) launch_2w<32>(grid, st, Xv, ldv, Xu, ldu, n, b, c, nsweeps, nsteps, log, wlog);
     else if (tw <= 64) launch_bt<64>(grid, st, Xv, ldv, Xu, ldu, n, b, c, nsweeps, nsteps, log, wlog);
     else return hipErrorInvalidValue;
     return hipGetLastError();
