@@ -8,7 +8,9 @@
 // order the reduction applied them) and V likewise from the right reflectors are
 // formed by X <- X H_i starting from X = I.
 //
-// A row x of X is independent of the other rows, so one thread owns one row.
+// A row x of X is independent of the other rows, so one thread owns one row
+// (for tiles up to 32 wide two threads, in two waves of one workgroup, own it,
+// each taking every other step of a stage; see bb_backtransform_2w).
 // Within a stage the reflectors are taken step by step in decreasing order and,
 // for each step j, sweep by sweep in increasing order: the support p..p+m of
 // (r, j), p = r + c + j b, then slides by one column per sweep, so the thread
